@@ -1,0 +1,261 @@
+/* tacaw.h - C ABI of the time auto-correlation (TACAW) hot-path library for gfx950 (MI355X).
+ *
+ * The method (Castellanos-Reyes, Zeiger, Rusz, arXiv 2401.15599): the electron beam is propagated by
+ * multislice through every snapshot tau(t) of a time-ordered atomic trajectory; the exit waves
+ * phi(q, t) are stacked into a (qx, qy, t) dataset, Fourier transformed from time to energy, squared,
+ * multiplied by the detailed-balance factor and normalised to a fractional intensity I(q, E).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: lengths in Angstrom, energies of the beam in eV, potentials in V*Angstrom (projected per
+ *   slice), times in fs, temperatures in K.
+ * Complex data: tacaw_c64 (interleaved float re, im).  Real data: float.  Positions: float x, y, z.
+ * Grids: nx, ny are powers of two in [16, 1024]; images are row-major [ny][nx] (x fastest).
+ *   Reciprocal-space images use DFT storage order: index m holds kx = m/Lx for m < nx/2 and
+ *   (m - nx)/Lx otherwise (likewise for y).
+ * Memory: "dev" pointers are device memory on the context's GPU, owned by the caller (for instance
+ *   torch tensors).  "host" pointers are read during the call only.  The library owns only its
+ *   workspace inside the context.
+ * Execution: every call is asynchronous on `stream` (a hipStream_t; NULL = the null stream) unless
+ *   stated otherwise; results are ready when the stream reaches the call.
+ * Errors: every call returns a tacaw_status.  Arguments are validated before any launch, so an
+ *   error other than TACAW_E_HIP leaves outputs unwritten.  tacaw_last_error() returns a message for
+ *   the calling thread's last failure.  No C++ exception crosses this interface.
+ * Threading: a context is not thread-safe; use one context per host thread.
+ * Determinism: reductions use a fixed order (no floating-point atomics); repeated calls with the
+ *   same inputs and the same tuning give bit-identical results.
+ */
+#ifndef TACAW_H
+#define TACAW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } tacaw_c64;
+
+typedef enum {
+  TACAW_OK = 0,
+  TACAW_E_ARG = -1,   /* null pointer, negative count, inconsistent sizes, unknown option */
+  TACAW_E_SIZE = -2,  /* a size outside what the kernels support (grid, segment length, species) */
+  TACAW_E_HIP = -3,   /* a HIP runtime call failed; message from tacaw_last_error() */
+  TACAW_E_NOMEM = -4, /* workspace allocation failed */
+  TACAW_E_STATE = -5  /* the context is unusable (wrong device, destroyed) */
+} tacaw_status;
+
+typedef struct tacaw_ctx tacaw_ctx;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int tacaw_version(void);
+
+/* Create a context bound to HIP device `hip_device`; *out receives it.  The context owns a growing
+ * workspace, the propagator/band-limit tables, cached launch plans and hipGraphs, and the FFT
+ * schedule choices (see tacaw_autotune).  Errors: TACAW_E_ARG (out NULL), TACAW_E_HIP. */
+int tacaw_create(int hip_device, tacaw_ctx** out);
+
+/* Free the context and everything it owns.  Waits for the device to finish work that uses the
+ * workspace.  NULL is accepted. */
+void tacaw_destroy(tacaw_ctx* ctx);
+
+/* Message of the calling thread's last failed call (empty string if none). */
+const char* tacaw_last_error(void);
+
+/* ----------------------------------------------------------------------------------------------
+ * Problem description (the paper's statement of the problem: positions of all nuclei per
+ * configuration, slices through the specimen on a numerical grid, beam energy and illumination,
+ * time step and the (q, E) output grid).
+ */
+typedef struct {
+  int32_t nx, ny;          /* grid, powers of two in [16, 1024] */
+  double lx, ly;           /* orthorhombic cell, periodic in x and y (Angstrom) */
+  int32_t n_slices;        /* S >= 1 */
+  const double* dz;        /* host [S] slice thicknesses (Angstrom), > 0 */
+  double z0;               /* entrance plane; slice s is [z_s, z_{s+1}), z_{s+1} = z_s + dz[s] */
+  double bandlimit;        /* band limit as a fraction of min(nx/(2lx), ny/(2ly)); <= 0: none */
+} tacaw_specimen;
+
+typedef struct {
+  double energy_ev;        /* beam energy (eV), > 0 */
+  int32_t kind;            /* TACAW_PLANE_WAVE or TACAW_PROBE */
+  double alpha_rad;        /* probe: convergence semi-angle (rad) */
+  double defocus_a;        /* probe: defocus (Angstrom), chi = pi lambda df k^2 + pi Cs lambda^3 k^4 / 2 */
+  double cs_a;             /* probe: spherical aberration (Angstrom) */
+  int32_t n_pos;           /* number of probe positions P (1 for a plane wave) */
+  const double* pos_xy;    /* host [P][2] probe positions (Angstrom); ignored for a plane wave */
+} tacaw_beam;
+
+enum { TACAW_PLANE_WAVE = 0, TACAW_PROBE = 1 };
+
+/* Scalar relations used by the library (host, synchronous).
+ * wavelength: lambda = hc / sqrt(E (2 m0c^2 + E)) (Angstrom);
+ * interaction parameter: sigma = (2 pi / (lambda E)) (m0c^2 + E) / (2 m0c^2 + E) (rad / (V Angstrom));
+ * energy axis: E_j = 2 pi hbar (j - n_e/2) / (n_e dt) (eV), j = 0..n_e-1 ascending, positive = loss
+ * (first step of the paper's two-step procedure: E_min = 2 pi hbar / t_tot, E_max = pi hbar / dt). */
+double tacaw_wavelength(double energy_ev);
+double tacaw_interaction_parameter(double energy_ev);
+int tacaw_energy_axis(int32_t n_e, double dt_fs, double* e_ev /* host [n_e] */);
+
+/* ----------------------------------------------------------------------------------------------
+ * Slice binning (textbook multislice slicing; the paper slices its specimens into hundreds of
+ * slices in its multislice runs).
+ * Atom j of snapshot t belongs to slice s when z_s <= z < z_{s+1}, decided in float64 with
+ * z_0 = z0 and z_{s+1} = z_s + dz[s] accumulated in slice order.  Atoms outside [z_0, z_S) belong to
+ * no slice and are dropped (counted in *n_outside).
+ *   xyz       dev [n_snap][n_atoms][3] float positions
+ *   species   dev [n_atoms] int32 in [0, n_species)
+ *   offsets   dev out [n_snap][S*n_species + 1] int32: atoms of (t, s, Z) are
+ *             order[t][offsets[t][s*n_species+Z] .. offsets[t][s*n_species+Z+1])
+ *   order     dev out [n_snap][n_atoms] int32 atom indices, sorted by (slice, species, index)
+ *   n_outside dev out [n_snap] int32 dropped atoms per snapshot, or NULL
+ * Integer results; identical to any correct stable binning.  Errors: TACAW_E_ARG, TACAW_E_SIZE
+ * (S * n_species > 16384). */
+int tacaw_bin_atoms(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap, int32_t n_atoms,
+                    const float* xyz, const int32_t* species, int32_t n_species, int32_t* offsets,
+                    int32_t* order, int32_t* n_outside, void* stream);
+
+/* Projected slice potentials of every snapshot.
+ *   V_s(k) = (2 pi a0 e / (Lx Ly)) M(k) sum_{j in s} f_{Z_j}(|k|) exp(-2 pi i k.r_j),
+ *   V_s(r) = Re sum_k V_s(k) exp(+2 pi i k.r) on the grid r = (x Lx/nx, y Ly/ny),
+ *   f_Z(q) = sum_i a_i/(q^2 + b_i) + sum_i c_i exp(-d_i q^2),  2 pi a0 e = 47.8777 V Angstrom^2,
+ *   M(k) = 1 when kx^2 + ky^2 < (bandlimit * kN)^2 (float64), else 0 (M = 1 if bandlimit <= 0).
+ * The paper computes phi(q, tau) "by a standard multislice method"; this is that textbook potential.
+ *   ff        host [n_species][12]: a1,b1,a2,b2,a3,b3,c1,d1,c2,d2,c3,d3 (q in 1/Angstrom)
+ *   V         dev out [n_snap][S][ny][nx] float (V Angstrom)
+ *   n_outside dev out [n_snap] int32 or NULL (as in tacaw_bin_atoms)
+ * Errors: TACAW_E_ARG, TACAW_E_SIZE (grid, n_species > 8), TACAW_E_NOMEM, TACAW_E_HIP. */
+int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap,
+                           int32_t n_atoms, const float* xyz, const int32_t* species,
+                           int32_t n_species, const double* ff, float* V, int32_t* n_outside,
+                           void* stream);
+
+/* Gradient of a loss with respect to the atoms' lateral positions, given dL/dV (the adjoint of
+ * tacaw_build_potentials at fixed slice membership):
+ *   dL/dx_j = Re sum_k conj(G_s(k)) C M(k) f_Zj(|k|) (-2 pi i kx) exp(-2 pi i k.r_j),  G_s = DFT[dL/dV_s]
+ * and likewise for y_j (dL/dz_j = 0: slice membership is piecewise constant in z).
+ *   grad_V   dev [n_snap][S][ny][nx] float
+ *   grad_xy  dev out [n_snap][n_atoms][2] float (atoms outside the slab get 0)
+ * Errors as tacaw_build_potentials. */
+int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap,
+                                    int32_t n_atoms, const float* xyz, const int32_t* species,
+                                    int32_t n_species, const double* ff, const float* grad_V,
+                                    float* grad_xy, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
+ * Batched multislice: the second step of the paper's procedure - the beam is propagated through
+ * every snapshot and the exit waves are accumulated into the dataset phi(qx, qy, t).
+ *   psi_{s+1} = F^-1[ M P_s F[ exp(i sigma V_s) psi_s ] ],  P_s(k) = exp(-i pi lambda dz_s |k|^2)
+ *   phi(q)    = M P_{S-1} F[ exp(i sigma V_{S-1}) psi_{S-1} ] / sqrt(nx ny)   (orthonormal)
+ * with F the unnormalised DFT exp(-2 pi i k.r).  psi_0 is a plane wave 1/sqrt(nx ny), or a probe
+ *   psi_0(k) ~ A(k) exp(-i chi(k)) exp(-2 pi i k.r_p),  A(k) = 1 iff lambda^2 (kx^2 + ky^2) <= alpha^2
+ * (float64), normalised to sum_r |psi_0|^2 = 1.
+ *
+ * One call runs a batch of jobs; job j has its own specimen, beam, trajectory length and buffers.
+ * Waves of the same snapshot (probe positions) share one read of V per slice.
+ */
+typedef struct {
+  const tacaw_specimen* spec;
+  const tacaw_beam* beam;
+  int32_t n_snap;          /* T_j */
+  const float* V;          /* dev [T_j][S][ny][nx] from tacaw_build_potentials */
+  tacaw_c64* exit;         /* dev out [T_j][P][ny][nx]: phi(q, t) in DFT order (also the working buffer) */
+  tacaw_c64* ckpt;         /* dev out [T_j][P][ceil(S/ckpt_stride)][ny][nx] checkpoints, or NULL */
+} tacaw_ms_job;
+
+enum {
+  TACAW_MODE_PLAIN = 0,    /* one snapshot per launch sequence: 2 launches per slice per snapshot */
+  TACAW_MODE_BATCHED = 1   /* every wave of a grid class in one launch per slice and pass; the
+                              slice loop is captured once into a hipGraph and replayed */
+};
+
+/* ckpt_stride: 0 = no checkpoints; k > 0 stores the wave entering slices 0, k, 2k, ... (the state
+ * needed by tacaw_multislice_adjoint; k = ceil(sqrt(S)) bounds memory by 2 sqrt(S) images per wave).
+ * Errors: TACAW_E_ARG, TACAW_E_SIZE, TACAW_E_NOMEM, TACAW_E_HIP. */
+int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs,
+                     int32_t ckpt_stride, int32_t mode, void* stream);
+
+/* Adjoint multislice: given G_phi = dL/dRe(phi) + i dL/dIm(phi) (the PyTorch convention, i.e.
+ * 2 dL/d conj(phi)) for every exit wave, accumulate dL/dV for every slice:
+ *   chi_{S-1} = F^-1[conj(M P_{S-1}) G_phi] sqrt(nx ny),  dL/dV_s = -sigma Im(conj(chi_s) t_s psi_s),
+ *   G_psi_s = conj(t_s) chi_s,  chi_{s-1} = F^-1[conj(M P_{s-1}) F[G_psi_s]],
+ * summed over probe positions.  psi_s is recomputed segment by segment from the checkpoints written
+ * by tacaw_multislice with the same ckpt_stride (so memory stays O(sqrt S) waves).
+ *   jobs[j].V, .ckpt as in the forward call; .exit is not used.
+ *   grad_exit  per job: dev [T_j][P][ny][nx] (read only)
+ *   grad_V     per job: dev out [T_j][S][ny][nx] float (overwritten)
+ * Errors as tacaw_multislice. */
+int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs,
+                             int32_t ckpt_stride, const tacaw_c64* const* grad_exit,
+                             float* const* grad_V, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
+ * Time auto-correlation spectrum (spectral decomposition, Kubo correction, convolution theorem and
+ * fractional normalisation of the paper).
+ *   Segment g covers snapshots g*hop .. g*hop+n_e-1, G = floor((T - n_e)/hop) + 1 (tail dropped).
+ *   Phi_g(q, k) = sum_t phi(q, g hop + t) exp(-2 pi i k t / n_e)   (rectangular window, no padding)
+ *   P(q, k) = (1/G) sum_g sum_p |Phi_g(q, k)|^2  (= DFT of the circular auto-correlation)
+ *   E_k = 2 pi hbar k' / (n_e dt), k' = k - n_e for k >= n_e/2 (the Nyquist bin is a gain)
+ *   K(E) = beta E / (1 - exp(-beta E)), K(0) = 1,  beta = 1/(k_B T)
+ *   I(q, E) = K P / Z,  Z = sum over the full q grid and all n_e bins of K P
+ * Output S[e][iy][ix] (float): energies ascending (bin e has k' = e - n_e/2), q centred (index i holds
+ * the signed frequency i - nq/2) and cropped to nqy_out x nqx_out.
+ */
+typedef struct {
+  double dt_fs;            /* snapshot spacing (fs) */
+  double temperature_k;    /* > 0 */
+  int32_t n_e;             /* segment length = energy bins, power of two in [8, 4096] */
+  int32_t hop;             /* segment offset >= 1 */
+  int32_t nqx_out, nqy_out;/* centred crop, 1..nx and 1..ny */
+} tacaw_spectrum_opts;
+
+/* Periodogram accumulation: P_acc[k][q] (+)= (1/G) sum_g sum_p |Phi_g(q, k)|^2 (DFT order, float).
+ *   exit   dev [n_snap][n_pos][ny][nx]
+ *   P_acc  dev [n_e][ny][nx] float; overwritten when accumulate == 0, added to otherwise (use this
+ *          to sum probe positions processed in chunks).
+ * Errors: TACAW_E_ARG, TACAW_E_SIZE (n_e), TACAW_E_HIP. */
+int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
+                      const tacaw_c64* exit, int32_t n_e, int32_t hop, float* P_acc,
+                      int32_t accumulate, void* stream);
+
+/* Kubo correction, normalisation, energy shift and q crop of an accumulated periodogram.
+ *   S     dev out [n_e][nqy_out][nqx_out] float
+ *   norm  dev out [1] double: Z, or NULL */
+int tacaw_spectrum_finalize(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* P_acc,
+                            const tacaw_spectrum_opts* opts, float* S, double* norm, void* stream);
+
+/* tacaw_periodogram (accumulate = 0) followed by tacaw_spectrum_finalize; P_acc lives in the
+ * workspace. */
+int tacaw_autocorr_spectrum(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
+                            const tacaw_c64* exit, const tacaw_spectrum_opts* opts, float* S,
+                            double* norm, void* stream);
+
+/* Adjoint of tacaw_autocorr_spectrum: from g = dL/dS (output grid) to G_phi (PyTorch convention):
+ *   dL/dP = (K/Z)(g - sum(g S)),  G_phi(g hop + t) += (2/G) sum_k dL/dP(k) Phi_g(k) exp(+2 pi i k t/n_e)
+ *   S, norm    the forward outputs (dev)
+ *   grad_S     dev [n_e][nqy_out][nqx_out] float
+ *   grad_exit  dev out [n_snap][n_pos][ny][nx] (snapshots in no segment get 0) */
+int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap,
+                                     int32_t n_pos, const tacaw_c64* exit,
+                                     const tacaw_spectrum_opts* opts, const float* S,
+                                     const double* norm, const float* grad_S,
+                                     tacaw_c64* grad_exit, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
+ * FFT schedule autotuning (the kernels' radix plan, lanes per line and columns per LDS tile).
+ * Times every compiled variant of the slice-step kernels for grid n (nx = ny = n) on a scratch batch
+ * of `n_waves` waves with HIP events, keeps the fastest per (n, pass) in the context and, when
+ * cache_path is not NULL, merges the choice into that JSON file (read back by tacaw_load_tuning).
+ * Synchronous (waits for the device).  Errors: TACAW_E_SIZE, TACAW_E_NOMEM, TACAW_E_HIP. */
+int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache_path,
+                   void* stream);
+/* Load tuning choices previously written by tacaw_autotune (host, synchronous).
+ * A missing file is not an error.  Errors: TACAW_E_ARG (malformed file). */
+int tacaw_load_tuning(tacaw_ctx* ctx, const char* cache_path);
+/* Current schedule for grid n as text ("row=<plan> col=<plan> C=<cols>"), for logging. */
+const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TACAW_H */

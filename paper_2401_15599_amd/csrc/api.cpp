@@ -1,0 +1,1160 @@
+// Host side of the C ABI declared in include/tacaw.h.
+//
+// Responsibilities: argument validation before any launch, float64 precomputation of the small
+// tables the kernels read (propagator factors, exact band-limit and aperture tables, slice
+// boundaries, Kubo factors), a content-addressed cache of those tables in device memory, grid-class
+// batching of uneven jobs, hipGraph capture of the batched slice loop, the checkpointed adjoint
+// schedule, and the FFT schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tacaw.h"
+#include "internal.hpp"
+
+namespace tacaw {
+hipError_t launch_position_grad_chunks(const PgArgs& a, const int4* chunks, int cap,
+                                       const int* count, hipStream_t st);
+int spectrum_q_tile(int n_e);
+hipError_t launch_chunk_list(const int* offsets, int t0, int n_snap_chunk, int S, int nsp,
+                             int4* chunks, int capacity, int* count, hipStream_t st);
+void prepare_dynamic_lds(int max_bytes);
+}  // namespace tacaw
+
+using namespace tacaw;
+
+// ------------------------------------------------------------------------------------------------
+// errors
+static thread_local std::string g_err;
+
+namespace {
+
+struct Fail {
+  int code;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) {
+  g_err = msg;
+  throw Fail{code};
+}
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(TACAW_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F> int guarded(F&& f) {
+  try {
+    f();
+    return TACAW_OK;
+  } catch (const Fail& x) {
+    return x.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return TACAW_E_NOMEM;
+  } catch (...) {
+    g_err = "unexpected error";
+    return TACAW_E_STATE;
+  }
+}
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+// ------------------------------------------------------------------------------------------------
+// physics (float64, host)
+constexpr double kHc = 12398.419843320026;     // eV Angstrom
+constexpr double kM0c2 = 510998.95;            // eV
+constexpr double kHbar = 0.6582119569;         // eV fs
+constexpr double kKb = 8.617333262e-5;         // eV/K
+constexpr double kA0 = 0.529177210903;         // Angstrom
+constexpr double kE4pe0 = 14.399645478425;     // V Angstrom
+constexpr double kPi = 3.14159265358979323846;
+
+double wavelength(double e) { return kHc / std::sqrt(e * (2.0 * kM0c2 + e)); }
+double sigma_of(double e) {
+  return (2.0 * kPi / (wavelength(e) * e)) * (kM0c2 + e) / (2.0 * kM0c2 + e);
+}
+int signed_index(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+// largest |n| kept in column m (or -1) for the predicate pred(kx, ky); pred must be monotone in |ky|
+template <class Pred> std::vector<int> column_limits(int nx, int ny, double lx, double ly, Pred pred) {
+  std::vector<int> out(nx, -1);
+  for (int m = 0; m < nx; ++m) {
+    const double kx = (double)signed_index(m, nx) / lx;
+    int best = -1;
+    for (int a = 0; a <= ny / 2; ++a) {
+      // both +a and -a (when they exist on the grid) share the same ky^2
+      const double ky = (double)a / ly;
+      if (pred(kx, ky)) best = a; else break;
+    }
+    out[m] = best;
+  }
+  return out;
+}
+
+std::vector<int> bandlimit_table(const tacaw_specimen& s) {
+  if (s.bandlimit <= 0.0) return std::vector<int>(s.nx, s.ny);   // keep everything
+  const double kn = std::min(s.nx / (2.0 * s.lx), s.ny / (2.0 * s.ly));
+  const double kmax = s.bandlimit * kn;
+  const double kmax2 = kmax * kmax;
+  return column_limits(s.nx, s.ny, s.lx, s.ly, [&](double kx, double ky) {
+    volatile double k2 = ky * ky + kx * kx;   // no contraction: same rounding as the reference
+    return k2 < kmax2;
+  });
+}
+
+std::vector<int> aperture_table(const tacaw_specimen& s, const tacaw_beam& b) {
+  const double lam = wavelength(b.energy_ev);
+  const double l2 = lam * lam, a2 = b.alpha_rad * b.alpha_rad;
+  return column_limits(s.nx, s.ny, s.lx, s.ly, [&](double kx, double ky) {
+    volatile double k2 = ky * ky + kx * kx;
+    volatile double lhs = l2 * k2;
+    return lhs <= a2;
+  });
+}
+
+// number of grid points kept by a column-limit table
+long count_kept(const std::vector<int>& t, int ny) {
+  long c = 0;
+  for (int v : t) {
+    if (v < 0) continue;
+    if (v >= ny / 2) c += ny; else c += 2 * v + 1;
+  }
+  return c;
+}
+
+std::vector<float2> propagator_axis(int n, double len, double lam, const double* dz, int S) {
+  std::vector<float2> out((size_t)S * n);
+  for (int s = 0; s < S; ++s)
+    for (int i = 0; i < n; ++i) {
+      const double k = (double)signed_index(i, n) / len;
+      const double ph = -kPi * lam * dz[s] * k * k;
+      out[(size_t)s * n + i] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+    }
+  return out;
+}
+
+std::vector<double> kubo_dft_order(int n_e, double dt, double temp) {
+  std::vector<double> k(n_e);
+  const double beta = 1.0 / (kKb * temp);
+  for (int i = 0; i < n_e; ++i) {
+    const int kp = i < n_e / 2 ? i : i - n_e;
+    const double e = 2.0 * kPi * kHbar * kp / (n_e * dt);
+    const double x = beta * e;
+    k[i] = std::fabs(x) < 1e-4 ? 1.0 + x / 2.0 + x * x / 12.0 : x / (-std::expm1(-x));
+  }
+  return k;
+}
+
+// ------------------------------------------------------------------------------------------------
+// device memory helpers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+struct Cached {
+  void* dev = nullptr;
+  void* host = nullptr;
+  size_t bytes = 0;
+};
+
+struct Sched {
+  int row_plan = 0, col_plan = 0, C = 0;
+};
+
+}  // namespace
+
+struct tacaw_ctx {
+  int device = 0;
+  int max_lds = 65536;
+  int n_cu = 256;
+  std::map<std::string, DevBuf> ws;
+  std::unordered_map<std::string, Cached> cache;
+  size_t cache_bytes = 0;
+  std::unordered_map<std::string, hipGraphExec_t> graphs;
+  std::map<int, Sched> sched;
+  hipStream_t cap_stream = nullptr;
+  std::string desc;
+
+  ~tacaw_ctx() {
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& c : cache) {
+      if (c.second.dev) (void)hipFree(c.second.dev);
+      if (c.second.host) (void)hipHostFree(c.second.host);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+namespace {
+
+void use_device(tacaw_ctx* c) {
+  if (!c) fail(TACAW_E_ARG, "null context");
+  hip_check(hipSetDevice(c->device), "hipSetDevice");
+}
+
+// grow-only named workspace; growing waits for the device so no queued kernel still uses it
+void* workspace(tacaw_ctx* c, const std::string& name, size_t bytes) {
+  DevBuf& b = c->ws[name];
+  if (b.bytes >= bytes && b.p) return b.p;
+  if (b.p) {
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    hip_check(hipFree(b.p), "hipFree");
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t sz = std::max<size_t>(bytes, 256);
+  if (hipMalloc(&b.p, sz) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    fail(TACAW_E_NOMEM, "workspace '" + name + "' of " + std::to_string(sz) + " bytes");
+  }
+  b.bytes = sz;
+  return b.p;
+}
+
+// content-addressed copy of a small host table in device memory (pinned staging kept alive)
+void* upload(tacaw_ctx* c, const void* data, size_t bytes, hipStream_t st, const char* tag) {
+  std::string key(tag);
+  key.append((const char*)data, bytes);
+  auto it = c->cache.find(key);
+  if (it != c->cache.end()) return it->second.dev;
+  if (c->cache_bytes > (256u << 20) || c->cache.size() > 4096) {
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    for (auto& e : c->cache) {
+      (void)hipFree(e.second.dev);
+      (void)hipHostFree(e.second.host);
+    }
+    c->cache.clear();
+    c->cache_bytes = 0;
+  }
+  Cached e;
+  e.bytes = bytes;
+  hip_check(hipHostMalloc(&e.host, std::max<size_t>(bytes, 16), hipHostMallocDefault), "hipHostMalloc");
+  std::memcpy(e.host, data, bytes);
+  hip_check(hipMalloc(&e.dev, std::max<size_t>(bytes, 16)), "hipMalloc");
+  hip_check(hipMemcpyAsync(e.dev, e.host, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+  c->cache.emplace(key, e);
+  c->cache_bytes += bytes;
+  return e.dev;
+}
+
+template <class T> T* upload_vec(tacaw_ctx* c, const std::vector<T>& v, hipStream_t st, const char* tag) {
+  return (T*)upload(c, v.data(), v.size() * sizeof(T), st, tag);
+}
+
+void validate_spec(const tacaw_specimen* s) {
+  if (!s) fail(TACAW_E_ARG, "null specimen");
+  if (!pow2_in(s->nx, 16, 1024) || !pow2_in(s->ny, 16, 1024))
+    fail(TACAW_E_SIZE, "grid must be powers of two in [16, 1024], got " + std::to_string(s->nx) +
+                           "x" + std::to_string(s->ny));
+  if (!(s->lx > 0) || !(s->ly > 0)) fail(TACAW_E_ARG, "cell lengths must be positive");
+  if (s->n_slices < 1 || !s->dz) fail(TACAW_E_ARG, "need n_slices >= 1 and dz");
+  for (int i = 0; i < s->n_slices; ++i)
+    if (!(s->dz[i] > 0)) fail(TACAW_E_ARG, "slice thickness must be positive");
+}
+
+void validate_beam(const tacaw_beam* b) {
+  if (!b) fail(TACAW_E_ARG, "null beam");
+  if (!(b->energy_ev > 0)) fail(TACAW_E_ARG, "beam energy must be positive");
+  if (b->kind != TACAW_PLANE_WAVE && b->kind != TACAW_PROBE) fail(TACAW_E_ARG, "unknown beam kind");
+  if (b->n_pos < 1) fail(TACAW_E_ARG, "n_pos must be >= 1");
+  if (b->kind == TACAW_PLANE_WAVE && b->n_pos != 1) fail(TACAW_E_ARG, "a plane wave has n_pos = 1");
+  if (b->kind == TACAW_PROBE && (!b->pos_xy || !(b->alpha_rad > 0)))
+    fail(TACAW_E_ARG, "a probe needs positions and alpha > 0");
+}
+
+Sched schedule_for(tacaw_ctx* c, int n) {
+  auto it = c->sched.find(n);
+  if (it != c->sched.end()) return it->second;
+  Sched s;
+  s.row_plan = 0;
+  s.col_plan = 0;
+  switch (n) {
+    case 16: s.C = 16; break;
+    case 32: s.C = 32; break;
+    case 64: s.C = 64; break;
+    case 128: s.C = 64; break;
+    case 256: s.C = 32; break;
+    case 512: s.C = 16; break;
+    default: s.C = 8; break;
+  }
+  return s;
+}
+
+int clamp_cols(tacaw_ctx* c, int ny, int plan, int C, int nx) {
+  C = std::min(C, nx);
+  while (C > 1 && col_lds_bytes(ny, plan, C) > c->max_lds) C /= 2;
+  return C;
+}
+
+// ------------------------------------------------------------------------------------------------
+// multislice planning
+struct ClassPlan {
+  int nx = 0, ny = 0;
+  std::vector<int2> groups;        // (job, t) sorted by S descending
+  std::vector<int4> waves;         // (job, t, p, S) same order
+  std::vector<int> group_S, wave_S;
+  std::vector<int4> plane_waves, probe_waves;
+  int Smax = 0;
+};
+
+int active_prefix(const std::vector<int>& S_sorted_desc, int s) {
+  // number of entries with S > s; upper_bound calls comp(value, element) and returns the first
+  // element for which it holds, i.e. the first element <= s in the descending list
+  return (int)(std::upper_bound(S_sorted_desc.begin(), S_sorted_desc.end(), s,
+                                [](int value, int element) { return element <= value; }) -
+               S_sorted_desc.begin());
+}
+
+struct MsBuild {
+  std::vector<MsJobDev> jobs;
+  std::vector<ClassPlan> classes;
+  MsJobDev* jobs_dev = nullptr;
+};
+
+MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_stride, hipStream_t st,
+                 bool adjoint, const tacaw_c64* const* gexit, float* const* gV) {
+  if (n_jobs < 1 || !jobs) fail(TACAW_E_ARG, "need at least one job");
+  if (ckpt_stride < 0) fail(TACAW_E_ARG, "ckpt_stride must be >= 0");
+  MsBuild b;
+  b.jobs.resize(n_jobs);
+  std::map<std::pair<int, int>, int> class_of;
+  for (int j = 0; j < n_jobs; ++j) {
+    const tacaw_ms_job& J = jobs[j];
+    validate_spec(J.spec);
+    validate_beam(J.beam);
+    if (J.n_snap < 1) fail(TACAW_E_ARG, "job " + std::to_string(j) + ": n_snap must be >= 1");
+    if (!J.V) fail(TACAW_E_ARG, "job " + std::to_string(j) + ": null V");
+    if (!adjoint && !J.exit) fail(TACAW_E_ARG, "job " + std::to_string(j) + ": null exit");
+    if (ckpt_stride > 0 && !J.ckpt) fail(TACAW_E_ARG, "job " + std::to_string(j) + ": null ckpt");
+    if (adjoint && (!gexit || !gexit[j] || !gV || !gV[j]))
+      fail(TACAW_E_ARG, "job " + std::to_string(j) + ": null gradient buffer");
+    const tacaw_specimen& S = *J.spec;
+    const tacaw_beam& B = *J.beam;
+    const double lam = wavelength(B.energy_ev);
+    MsJobDev d{};
+    d.V = J.V;
+    d.W = (float2*)J.exit;
+    d.ckpt = (float2*)J.ckpt;
+    d.px = upload_vec(c, propagator_axis(S.nx, S.lx, lam, S.dz, S.n_slices), st, "px");
+    d.py = upload_vec(c, propagator_axis(S.ny, S.ly, lam, S.dz, S.n_slices), st, "py");
+    d.nmax = upload_vec(c, bandlimit_table(S), st, "bl");
+    long n_ap = 1;
+    if (B.kind == TACAW_PROBE) {
+      std::vector<int> ap = aperture_table(S, B);
+      n_ap = count_kept(ap, S.ny);
+      if (n_ap < 1) fail(TACAW_E_ARG, "probe aperture holds no grid point");
+      d.nap = upload_vec(c, ap, st, "ap");
+      std::vector<double> pxy(B.pos_xy, B.pos_xy + 2 * B.n_pos);
+      d.pxy = upload_vec(c, pxy, st, "pxy");
+    }
+    d.T = J.n_snap;
+    d.P = B.n_pos;
+    d.S = S.n_slices;
+    d.nx = S.nx;
+    d.ny = S.ny;
+    d.ck_stride = ckpt_stride > 0 ? ckpt_stride : 1;
+    d.n_ck = ckpt_stride > 0 ? (S.n_slices + ckpt_stride - 1) / ckpt_stride : 0;
+    d.stash_k = ckpt_stride > 0 ? ckpt_stride : 1;
+    d.sigma = (float)sigma_of(B.energy_ev);
+    const double npix = (double)S.nx * S.ny;
+    d.scale_mid = (float)(1.0 / npix);
+    d.scale_last = (float)(1.0 / std::sqrt(npix));
+    d.scale_probe = (float)(1.0 / (std::sqrt(npix) * std::sqrt((double)n_ap)));
+    d.lx = S.lx;
+    d.ly = S.ly;
+    d.lambda = lam;
+    d.defocus = B.defocus_a;
+    d.cs = B.cs_a;
+    if (adjoint) {
+      d.gexit = (const float2*)gexit[j];
+      d.gV = gV[j];
+    }
+    b.jobs[j] = d;
+    auto key = std::make_pair(S.nx, S.ny);
+    if (!class_of.count(key)) {
+      class_of[key] = (int)b.classes.size();
+      b.classes.emplace_back();
+      b.classes.back().nx = S.nx;
+      b.classes.back().ny = S.ny;
+    }
+  }
+  for (int j = 0; j < n_jobs; ++j) {
+    ClassPlan& cp = b.classes[class_of[{b.jobs[j].nx, b.jobs[j].ny}]];
+    for (int t = 0; t < b.jobs[j].T; ++t) cp.groups.push_back(make_int2(j, t));
+  }
+  for (auto& cp : b.classes) {
+    std::stable_sort(cp.groups.begin(), cp.groups.end(), [&](int2 a, int2 x) {
+      return b.jobs[a.x].S > b.jobs[x.x].S;
+    });
+    for (auto g : cp.groups) {
+      const MsJobDev& d = b.jobs[g.x];
+      cp.group_S.push_back(d.S);
+      for (int p = 0; p < d.P; ++p) {
+        int4 w = make_int4(g.x, g.y, p, d.S);
+        cp.waves.push_back(w);
+        cp.wave_S.push_back(d.S);
+        if (jobs[g.x].beam->kind == TACAW_PROBE) cp.probe_waves.push_back(w);
+        else cp.plane_waves.push_back(w);
+      }
+    }
+    cp.Smax = cp.group_S.empty() ? 0 : cp.group_S.front();
+  }
+  return b;
+}
+
+struct Launcher {
+  tacaw_ctx* c;
+  hipStream_t st;
+  void row(int n, const Sched& sc, bool adj, RowArgs a) {
+    if (a.n_groups <= 0) return;
+    const int lines = row_lines_per_wave(n, sc.row_plan);
+    const long tasks = (long)a.n_groups * a.ny;
+    long g = (tasks + (long)kWaves * lines - 1) / ((long)kWaves * lines);
+    g = std::min<long>(g, (long)c->n_cu * 8);
+    hip_check(launch_row(n, sc.row_plan, adj, a, (int)std::max<long>(g, 1), st), "row kernel");
+  }
+  void col(int ny, const Sched& sc, bool f, bool i, ColArgs a) {
+    if (a.n_waves <= 0) return;
+    const long tasks = (long)a.n_waves * (a.nx / a.C);
+    long g = std::min<long>(tasks, (long)c->n_cu * 8);
+    hip_check(launch_col(ny, sc.col_plan, f, i, a, (int)std::max<long>(g, 1), st), "column kernel");
+  }
+};
+
+void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipStream_t st) {
+  Launcher L{c, st};
+  for (const ClassPlan& cp : b.classes) {
+    const Sched rs = schedule_for(c, cp.nx);
+    Sched cs = schedule_for(c, cp.ny);
+    cs.C = clamp_cols(c, cp.ny, cs.col_plan, cs.C, cp.nx);
+    auto do_range = [&](const int2* groups, int ng, const int4* waves, const std::vector<int>& gS,
+                        const std::vector<int>& wS, const int4* plane, int nplane,
+                        const int4* probe, int nprobe) {
+      ColArgs ia{};
+      ia.jobs = b.jobs_dev;
+      ia.out_buf = BUF_W;
+      ia.C = cs.C;
+      ia.nx = cp.nx;
+      if (nplane > 0) {
+        ia.waves = plane;
+        ia.n_waves = nplane;
+        long g = std::min<long>(nplane, (long)c->n_cu * 8);
+        hip_check(launch_plane_init(ia, (int)g, st), "plane-wave init");
+      }
+      if (nprobe > 0) {
+        ia.waves = probe;
+        ia.n_waves = nprobe;
+        long g = std::min<long>((long)nprobe * (cp.nx / cs.C), (long)c->n_cu * 8);
+        hip_check(launch_probe_init(cp.ny, cs.col_plan, ia, (int)g, st), "probe init");
+      }
+      const int Smax = gS.empty() ? 0 : gS.front();
+      for (int s = 0; s < Smax; ++s) {
+        RowArgs ra{};
+        ra.jobs = b.jobs_dev;
+        ra.groups = groups;
+        ra.n_groups = active_prefix(gS, s);
+        ra.s = s;
+        ra.in_buf = BUF_W;
+        ra.out_buf = BUF_W;
+        ra.store_ckpt = (ckpt_stride > 0 && s % ckpt_stride == 0) ? 1 : 0;
+        ra.stash_slot = -1;
+        ra.write_out = 1;
+        ra.ny = cp.ny;
+        L.row(cp.nx, rs, false, ra);
+        const int n_mid = active_prefix(wS, s + 1), n_all = active_prefix(wS, s);
+        ColArgs ca{};
+        ca.jobs = b.jobs_dev;
+        ca.s = s;
+        ca.in_buf = BUF_W;
+        ca.out_buf = BUF_W;
+        ca.conj_prop = 0;
+        ca.C = cs.C;
+        ca.nx = cp.nx;
+        if (n_mid > 0) {
+          ca.waves = waves;
+          ca.n_waves = n_mid;
+          ca.scale = (float)(1.0 / ((double)cp.nx * cp.ny));
+          L.col(cp.ny, cs, true, true, ca);
+        }
+        if (n_all > n_mid) {
+          ca.waves = waves + n_mid;
+          ca.n_waves = n_all - n_mid;
+          ca.scale = (float)(1.0 / std::sqrt((double)cp.nx * cp.ny));
+          L.col(cp.ny, cs, true, false, ca);
+        }
+      }
+    };
+    // device copies of the class lists
+    int2* groups_dev = upload_vec(c, cp.groups, st, "groups");
+    int4* waves_dev = upload_vec(c, cp.waves, st, "waves");
+    int4* plane_dev = cp.plane_waves.empty() ? nullptr : upload_vec(c, cp.plane_waves, st, "pw");
+    int4* probe_dev = cp.probe_waves.empty() ? nullptr : upload_vec(c, cp.probe_waves, st, "pr");
+    if (mode == TACAW_MODE_PLAIN) {
+      // one snapshot (all its probe positions) per launch sequence
+      size_t wi = 0;
+      for (size_t gi = 0; gi < cp.groups.size(); ++gi) {
+        const MsJobDev& d = b.jobs[cp.groups[gi].x];
+        std::vector<int> gS(1, d.S), wS(d.P, d.S);
+        const bool probe = d.nap != nullptr;
+        // the group's waves are contiguous in the class wave list and in the init lists
+        const int4* w = waves_dev + wi;
+        do_range(groups_dev + gi, 1, w, gS, wS, probe ? nullptr : w, probe ? 0 : d.P,
+                 probe ? w : nullptr, probe ? d.P : 0);
+        wi += d.P;
+      }
+    } else {
+      do_range(groups_dev, (int)cp.groups.size(), waves_dev, cp.group_S, cp.wave_S, plane_dev,
+               (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size());
+    }
+  }
+}
+
+std::string graph_key(const MsBuild& b, int ckpt_stride, int mode, tacaw_ctx* c) {
+  std::string k((const char*)b.jobs.data(), b.jobs.size() * sizeof(MsJobDev));
+  k += "|" + std::to_string(ckpt_stride) + "|" + std::to_string(mode);
+  for (auto& cp : b.classes) {
+    Sched a = schedule_for(c, cp.nx), s2 = schedule_for(c, cp.ny);
+    k += "|" + std::to_string(cp.nx) + "," + std::to_string(a.row_plan) + "," +
+         std::to_string(s2.col_plan) + "," + std::to_string(s2.C);
+    k.append((const char*)cp.groups.data(), cp.groups.size() * sizeof(int2));
+  }
+  return k;
+}
+
+}  // namespace
+
+// =================================================================================================
+extern "C" {
+
+int tacaw_version(void) { return 100; }
+
+const char* tacaw_last_error(void) { return g_err.c_str(); }
+
+int tacaw_create(int hip_device, tacaw_ctx** out) {
+  return guarded([&] {
+    if (!out) fail(TACAW_E_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    if (hip_device < 0 || hip_device >= n) fail(TACAW_E_ARG, "no such HIP device");
+    hip_check(hipSetDevice(hip_device), "hipSetDevice");
+    auto c = std::make_unique<tacaw_ctx>();
+    c->device = hip_device;
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties");
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess &&
+        lds > 0)
+      c->max_lds = lds;
+    hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    prepare_dynamic_lds(c->max_lds);
+    const char* tc = std::getenv("TACAW_TUNE_CACHE");
+    if (tc && *tc) tacaw_load_tuning(c.get(), tc);
+    *out = c.release();
+  });
+}
+
+void tacaw_destroy(tacaw_ctx* ctx) { delete ctx; }
+
+double tacaw_wavelength(double e) { return wavelength(e); }
+double tacaw_interaction_parameter(double e) { return sigma_of(e); }
+
+int tacaw_energy_axis(int32_t n_e, double dt_fs, double* e_ev) {
+  return guarded([&] {
+    if (n_e < 1 || !(dt_fs > 0) || !e_ev) fail(TACAW_E_ARG, "bad energy-axis arguments");
+    for (int j = 0; j < n_e; ++j) e_ev[j] = 2.0 * kPi * kHbar * (j - n_e / 2) / (n_e * dt_fs);
+  });
+}
+
+// ------------------------------------------------------------------------------------------------
+static std::vector<double> slice_bounds(const tacaw_specimen& s) {
+  std::vector<double> b(s.n_slices + 1);
+  b[0] = s.z0;
+  for (int i = 0; i < s.n_slices; ++i) {
+    volatile double nb = b[i] + s.dz[i];
+    b[i + 1] = nb;
+  }
+  return b;
+}
+
+static void validate_atoms(const tacaw_specimen* spec, int n_snap, int n_atoms, const float* xyz,
+                           const int* species, int n_species) {
+  validate_spec(spec);
+  if (n_snap < 1 || n_atoms < 1) fail(TACAW_E_ARG, "need n_snap >= 1 and n_atoms >= 1");
+  if (!xyz || !species) fail(TACAW_E_ARG, "null positions or species");
+  if (n_species < 1 || n_species > kMaxSpecies) fail(TACAW_E_SIZE, "n_species must be in [1, 8]");
+  if ((long)spec->n_slices * n_species > 16384) fail(TACAW_E_SIZE, "n_slices * n_species > 16384");
+}
+
+int tacaw_bin_atoms(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap, int32_t n_atoms,
+                    const float* xyz, const int32_t* species, int32_t n_species, int32_t* offsets,
+                    int32_t* order, int32_t* n_outside, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_atoms(spec, n_snap, n_atoms, xyz, species, n_species);
+    if (!offsets || !order) fail(TACAW_E_ARG, "null outputs");
+    hipStream_t st = (hipStream_t)stream;
+    double* bnd = upload_vec(ctx, slice_bounds(*spec), st, "bounds");
+    hip_check(launch_bin_atoms(xyz, species, n_snap, n_atoms, n_species, bnd, spec->n_slices,
+                               offsets, order, n_outside, st),
+              "bin kernel");
+  });
+}
+
+static std::vector<float> ff_f32(const double* ff, int nsp) {
+  std::vector<float> f(12 * nsp);
+  for (int i = 0; i < 12 * nsp; ++i) f[i] = (float)ff[i];
+  return f;
+}
+
+int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap,
+                           int32_t n_atoms, const float* xyz, const int32_t* species,
+                           int32_t n_species, const double* ff, float* V, int32_t* n_outside,
+                           void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_atoms(spec, n_snap, n_atoms, xyz, species, n_species);
+    if (!ff || !V) fail(TACAW_E_ARG, "null form factors or output");
+    for (int i = 0; i < 12 * n_species; ++i)
+      if (!std::isfinite(ff[i])) fail(TACAW_E_ARG, "form-factor coefficients must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    const int S = spec->n_slices, K = S * n_species;
+    int* offs = (int*)workspace(ctx, "offsets", (size_t)n_snap * (K + 1) * sizeof(int));
+    int* ord = (int*)workspace(ctx, "order", (size_t)n_snap * n_atoms * sizeof(int));
+    double* bnd = upload_vec(ctx, slice_bounds(*spec), st, "bounds");
+    hip_check(launch_bin_atoms(xyz, species, n_snap, n_atoms, n_species, bnd, S, offs, ord,
+                               n_outside, st),
+              "bin kernel");
+    float* ffd = upload_vec(ctx, ff_f32(ff, n_species), st, "ff");
+    int* nmax = upload_vec(ctx, bandlimit_table(*spec), st, "bl");
+    const size_t img = (size_t)spec->nx * spec->ny;
+    const size_t budget = (size_t)1 << 30;   // bytes of complex k-space maps per pass
+    int snaps_per = (int)std::max<size_t>(1, budget / (img * 8 * S));
+    snaps_per = std::min(snaps_per, (int)n_snap);
+    float2* vk = (float2*)workspace(ctx, "vk", (size_t)snaps_per * S * img * sizeof(float2));
+    for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
+      const int nt = std::min(snaps_per, n_snap - t0);
+      SfArgs a{};
+      a.xyz = xyz;
+      a.order = ord;
+      a.offsets = offs;
+      a.ff = ffd;
+      a.vk = vk;
+      a.t0 = t0;
+      a.s_count = S;
+      a.n_atoms = n_atoms;
+      a.n_species = n_species;
+      a.nx = spec->nx;
+      a.ny = spec->ny;
+      a.lx = spec->lx;
+      a.ly = spec->ly;
+      a.pref = (float)(2.0 * kPi * kA0 * kE4pe0 / (spec->lx * spec->ly));
+      a.nmax = nmax;
+      a.n_maps = nt * S;
+      hip_check(launch_structure_factor(a, st), "structure-factor kernel");
+      hip_check(launch_ifft2_real(spec->nx, spec->ny, vk, V + (size_t)t0 * S * img, nt * S, st),
+                "potential inverse FFT");
+    }
+  });
+}
+
+int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap,
+                                    int32_t n_atoms, const float* xyz, const int32_t* species,
+                                    int32_t n_species, const double* ff, const float* grad_V,
+                                    float* grad_xy, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_atoms(spec, n_snap, n_atoms, xyz, species, n_species);
+    if (!ff || !grad_V || !grad_xy) fail(TACAW_E_ARG, "null form factors or gradient buffers");
+    hipStream_t st = (hipStream_t)stream;
+    const int S = spec->n_slices, K = S * n_species;
+    int* offs = (int*)workspace(ctx, "offsets", (size_t)n_snap * (K + 1) * sizeof(int));
+    int* ord = (int*)workspace(ctx, "order", (size_t)n_snap * n_atoms * sizeof(int));
+    double* bnd = upload_vec(ctx, slice_bounds(*spec), st, "bounds");
+    hip_check(launch_bin_atoms(xyz, species, n_snap, n_atoms, n_species, bnd, S, offs, ord,
+                               nullptr, st),
+              "bin kernel");
+    hip_check(launch_zero(grad_xy, (size_t)n_snap * n_atoms * 2 * sizeof(float), st), "zero");
+    float* ffd = upload_vec(ctx, ff_f32(ff, n_species), st, "ff");
+    int* nmax = upload_vec(ctx, bandlimit_table(*spec), st, "bl");
+    const size_t img = (size_t)spec->nx * spec->ny;
+    const size_t budget = (size_t)1 << 30;
+    int snaps_per = (int)std::max<size_t>(1, budget / (img * 8 * S));
+    snaps_per = std::min(snaps_per, (int)n_snap);
+    float2* gk = (float2*)workspace(ctx, "vk", (size_t)snaps_per * S * img * sizeof(float2));
+    const int cap = snaps_per * K + (int)(((long)snaps_per * n_atoms + 63) / 64) + 1;
+    int4* chunks = (int4*)workspace(ctx, "chunks", (size_t)cap * sizeof(int4) + 16);
+    int* count = (int*)(chunks + cap);
+    for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
+      const int nt = std::min(snaps_per, n_snap - t0);
+      hip_check(launch_fft2_real(spec->nx, spec->ny, grad_V + (size_t)t0 * S * img, gk, nt * S, st),
+                "gradient FFT");
+      hip_check(launch_chunk_list(offs, t0, nt, S, n_species, chunks, cap, count, st), "chunk list");
+      PgArgs a{};
+      a.xyz = xyz;
+      a.order = ord;
+      a.offsets = offs;
+      a.ff = ffd;
+      a.gk = gk;
+      a.gxy = grad_xy;
+      a.t0 = t0;
+      a.s_count = S;
+      a.n_atoms = n_atoms;
+      a.n_species = n_species;
+      a.nx = spec->nx;
+      a.ny = spec->ny;
+      a.n_maps = nt * S;
+      a.lx = spec->lx;
+      a.ly = spec->ly;
+      a.pref = (float)(2.0 * kPi * kA0 * kE4pe0 / (spec->lx * spec->ly));
+      a.nmax = nmax;
+      hip_check(launch_position_grad_chunks(a, chunks, cap, count, st), "position-gradient kernel");
+    }
+  });
+}
+
+// ------------------------------------------------------------------------------------------------
+int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, int32_t ckpt_stride,
+                     int32_t mode, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    if (mode != TACAW_MODE_PLAIN && mode != TACAW_MODE_BATCHED) fail(TACAW_E_ARG, "unknown mode");
+    hipStream_t st = (hipStream_t)stream;
+    MsBuild b = build_ms(ctx, n_jobs, jobs, ckpt_stride, st, false, nullptr, nullptr);
+    b.jobs_dev = upload_vec(ctx, b.jobs, st, "jobs");
+    if (mode == TACAW_MODE_PLAIN) {
+      run_forward(ctx, b, ckpt_stride, mode, st);
+      return;
+    }
+    const std::string key = graph_key(b, ckpt_stride, mode, ctx);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+      // lists must be resident before capture (uploads are not captured)
+      for (auto& cp : b.classes) {
+        upload_vec(ctx, cp.groups, st, "groups");
+        upload_vec(ctx, cp.waves, st, "waves");
+        if (!cp.plane_waves.empty()) upload_vec(ctx, cp.plane_waves, st, "pw");
+        if (!cp.probe_waves.empty()) upload_vec(ctx, cp.probe_waves, st, "pr");
+      }
+      hipGraph_t g = nullptr;
+      hip_check(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
+                "hipStreamBeginCapture");
+      try {
+        run_forward(ctx, b, ckpt_stride, mode, ctx->cap_stream);
+      } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(ctx->cap_stream, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(ctx->cap_stream, &g), "hipStreamEndCapture");
+      hipGraphExec_t ex = nullptr;
+      hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      hip_check(e, "hipGraphInstantiate");
+      it = ctx->graphs.emplace(key, ex).first;
+    }
+    hip_check(hipGraphLaunch(it->second, st), "hipGraphLaunch");
+  });
+}
+
+int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs,
+                             int32_t ckpt_stride, const tacaw_c64* const* grad_exit,
+                             float* const* grad_V, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    if (ckpt_stride < 1) fail(TACAW_E_ARG, "the adjoint needs the forward checkpoints (stride >= 1)");
+    hipStream_t st = (hipStream_t)stream;
+    MsBuild b = build_ms(ctx, n_jobs, jobs, ckpt_stride, st, true, grad_exit, grad_V);
+    // workspace per job: adjoint state, recompute buffer, stash of one segment
+    size_t total = 0;
+    std::vector<size_t> offs(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+      const MsJobDev& d = b.jobs[j];
+      const size_t img = (size_t)d.nx * d.ny * sizeof(float2);
+      offs[j] = total;
+      total += img * d.T * d.P * (2 + ckpt_stride);
+    }
+    char* base = (char*)workspace(ctx, "adjoint", total);
+    for (int j = 0; j < n_jobs; ++j) {
+      MsJobDev& d = b.jobs[j];
+      const size_t img = (size_t)d.nx * d.ny * sizeof(float2);
+      const size_t n = (size_t)d.T * d.P;
+      d.adj = (float2*)(base + offs[j]);
+      d.rec = (float2*)(base + offs[j] + img * n);
+      d.stash = (float2*)(base + offs[j] + 2 * img * n);
+    }
+    b.jobs_dev = upload_vec(ctx, b.jobs, st, "jobs");
+    Launcher L{ctx, st};
+    for (const ClassPlan& cp : b.classes) {
+      const Sched rs = schedule_for(ctx, cp.nx);
+      Sched cs = schedule_for(ctx, cp.ny);
+      cs.C = clamp_cols(ctx, cp.ny, cs.col_plan, cs.C, cp.nx);
+      // process jobs of equal slice count together: segments then align
+      std::map<int, std::pair<std::vector<int2>, std::vector<int4>>, std::greater<int>> byS;
+      for (auto g : cp.groups) byS[b.jobs[g.x].S].first.push_back(g);
+      for (auto w : cp.waves) byS[b.jobs[w.x].S].second.push_back(w);
+      for (auto& kv : byS) {
+        const int S = kv.first;
+        int2* groups = upload_vec(ctx, kv.second.first, st, "groups");
+        int4* waves = upload_vec(ctx, kv.second.second, st, "waves");
+        const int ng = (int)kv.second.first.size(), nw = (int)kv.second.second.size();
+        const float scale_mid = (float)(1.0 / ((double)cp.nx * cp.ny));
+        const float scale_last = (float)(1.0 / std::sqrt((double)cp.nx * cp.ny));
+        ColArgs ca{};
+        ca.jobs = b.jobs_dev;
+        ca.waves = waves;
+        ca.n_waves = nw;
+        ca.C = cs.C;
+        ca.nx = cp.nx;
+        // chi_{S-1} in (kx, y): G_y[conj(M P_{S-1}) G_phi] / sqrt(N)
+        ca.s = S - 1;
+        ca.in_buf = BUF_GEXIT;
+        ca.out_buf = BUF_ADJ;
+        ca.conj_prop = 1;
+        ca.scale = scale_last;
+        L.col(cp.ny, cs, false, true, ca);
+        const int nck = (S + ckpt_stride - 1) / ckpt_stride;
+        for (int c = nck - 1; c >= 0; --c) {
+          const int s0 = c * ckpt_stride, s1 = std::min(S, s0 + ckpt_stride);
+          for (int s = s0; s < s1; ++s) {
+            RowArgs ra{};
+            ra.jobs = b.jobs_dev;
+            ra.groups = groups;
+            ra.n_groups = ng;
+            ra.s = s;
+            ra.in_buf = (s == s0) ? BUF_CKPT : BUF_REC;
+            ra.out_buf = BUF_REC;
+            ra.store_ckpt = 0;
+            ra.stash_slot = s - s0;
+            ra.write_out = (s < s1 - 1) ? 1 : 0;
+            ra.ny = cp.ny;
+            L.row(cp.nx, rs, false, ra);
+            if (s < s1 - 1) {
+              ColArgs fa = ca;
+              fa.s = s;
+              fa.in_buf = BUF_REC;
+              fa.out_buf = BUF_REC;
+              fa.conj_prop = 0;
+              fa.scale = scale_mid;
+              L.col(cp.ny, cs, true, true, fa);
+            }
+          }
+          for (int s = s1 - 1; s >= s0; --s) {
+            RowArgs ra{};
+            ra.jobs = b.jobs_dev;
+            ra.groups = groups;
+            ra.n_groups = ng;
+            ra.s = s;
+            ra.in_buf = BUF_ADJ;
+            ra.out_buf = BUF_ADJ;
+            ra.store_ckpt = 0;
+            ra.stash_slot = s - s0;
+            ra.write_out = s > 0 ? 1 : 0;
+            ra.ny = cp.ny;
+            L.row(cp.nx, rs, true, ra);
+            if (s > 0) {
+              ColArgs aa = ca;
+              aa.s = s - 1;
+              aa.in_buf = BUF_ADJ;
+              aa.out_buf = BUF_ADJ;
+              aa.conj_prop = 1;
+              aa.scale = scale_mid;
+              L.col(cp.ny, cs, true, true, aa);
+            }
+          }
+        }
+      }
+    }
+  });
+}
+
+// ------------------------------------------------------------------------------------------------
+static void validate_spectrum(int nx, int ny, int n_snap, int n_pos, const tacaw_c64* exit,
+                              int n_e, int hop) {
+  if (!pow2_in(nx, 16, 1024) || !pow2_in(ny, 16, 1024)) fail(TACAW_E_SIZE, "grid size");
+  if (n_snap < 1 || n_pos < 1 || !exit) fail(TACAW_E_ARG, "bad exit stack");
+  if (!pow2_in(n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
+  if (hop < 1) fail(TACAW_E_ARG, "hop must be >= 1");
+  if (n_e > n_snap) fail(TACAW_E_ARG, "segment longer than the trajectory");
+}
+
+int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
+                      const tacaw_c64* exit, int32_t n_e, int32_t hop, float* P_acc,
+                      int32_t accumulate, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_spectrum(nx, ny, n_snap, n_pos, exit, n_e, hop);
+    if (!P_acc) fail(TACAW_E_ARG, "null P_acc");
+    SpecArgs a{};
+    a.exit = (const float2*)exit;
+    a.P = P_acc;
+    a.T = n_snap;
+    a.Pn = n_pos;
+    a.nq = nx * ny;
+    a.n_e = n_e;
+    a.hop = hop;
+    a.G = (n_snap - n_e) / hop + 1;
+    a.accumulate = accumulate ? 1 : 0;
+    hip_check(launch_periodogram(a, (hipStream_t)stream), "periodogram kernel");
+  });
+}
+
+static void validate_opts(const tacaw_spectrum_opts* o, int nx, int ny) {
+  if (!o) fail(TACAW_E_ARG, "null spectrum options");
+  if (!(o->dt_fs > 0) || !(o->temperature_k > 0)) fail(TACAW_E_ARG, "dt and temperature must be > 0");
+  if (o->nqx_out < 1 || o->nqx_out > nx || o->nqy_out < 1 || o->nqy_out > ny)
+    fail(TACAW_E_ARG, "output crop outside the q grid");
+}
+
+int tacaw_spectrum_finalize(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* P_acc,
+                            const tacaw_spectrum_opts* opts, float* S, double* norm, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_opts(opts, nx, ny);
+    if (!pow2_in(opts->n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
+    if (!P_acc || !S) fail(TACAW_E_ARG, "null buffers");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> kd = kubo_dft_order(opts->n_e, opts->dt_fs, opts->temperature_k);
+    std::vector<float> kf(kd.begin(), kd.end());
+    FinArgs a{};
+    a.P = P_acc;
+    a.K = upload_vec(ctx, kf, st, "kubo");
+    a.S = S;
+    a.n_part = 512;
+    double* part = (double*)workspace(ctx, "partial", (a.n_part + 2) * sizeof(double));
+    a.partial = part;
+    a.norm = norm ? norm : part + a.n_part;
+    a.n_e = opts->n_e;
+    a.nx = nx;
+    a.ny = ny;
+    a.nqx = opts->nqx_out;
+    a.nqy = opts->nqy_out;
+    hip_check(launch_finalize(a, st), "finalize kernels");
+  });
+}
+
+int tacaw_autocorr_spectrum(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
+                            const tacaw_c64* exit, const tacaw_spectrum_opts* opts, float* S,
+                            double* norm, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_opts(opts, nx, ny);
+    validate_spectrum(nx, ny, n_snap, n_pos, exit, opts->n_e, opts->hop);
+    if (!S) fail(TACAW_E_ARG, "null S");
+    float* P = (float*)workspace(ctx, "pacc", (size_t)opts->n_e * nx * ny * sizeof(float));
+    int r = tacaw_periodogram(ctx, nx, ny, n_snap, n_pos, exit, opts->n_e, opts->hop, P, 0, stream);
+    if (r != TACAW_OK) throw Fail{r};
+    r = tacaw_spectrum_finalize(ctx, nx, ny, P, opts, S, norm, stream);
+    if (r != TACAW_OK) throw Fail{r};
+  });
+}
+
+int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap,
+                                     int32_t n_pos, const tacaw_c64* exit,
+                                     const tacaw_spectrum_opts* opts, const float* S,
+                                     const double* norm, const float* grad_S,
+                                     tacaw_c64* grad_exit, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_opts(opts, nx, ny);
+    validate_spectrum(nx, ny, n_snap, n_pos, exit, opts->n_e, opts->hop);
+    if (!S || !norm || !grad_S || !grad_exit) fail(TACAW_E_ARG, "null buffers");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> kd = kubo_dft_order(opts->n_e, opts->dt_fs, opts->temperature_k);
+    std::vector<float> kf(kd.begin(), kd.end());
+    SpecBwdArgs a{};
+    a.exit = (const float2*)exit;
+    a.S = S;
+    a.norm = norm;
+    a.gS = grad_S;
+    a.K = upload_vec(ctx, kf, st, "kubo");
+    a.gexit = (float2*)grad_exit;
+    a.n_part = 512;
+    a.partial = (double*)workspace(ctx, "partial_b", (a.n_part + 2) * sizeof(double));
+    a.T = n_snap;
+    a.Pn = n_pos;
+    a.nx = nx;
+    a.ny = ny;
+    a.nq = nx * ny;
+    a.n_e = opts->n_e;
+    a.hop = opts->hop;
+    a.G = (n_snap - opts->n_e) / opts->hop + 1;
+    a.nqx = opts->nqx_out;
+    a.nqy = opts->nqy_out;
+    hip_check(launch_spectrum_backward(a, st), "spectrum backward");
+  });
+}
+
+// ------------------------------------------------------------------------------------------------
+// autotuning
+static std::string sched_line(int n, const Sched& s) {
+  std::ostringstream o;
+  o << "row=" << plan_name(n, s.row_plan) << " col=" << plan_name(n, s.col_plan) << " C=" << s.C;
+  return o.str();
+}
+
+const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n) {
+  if (!ctx || !pow2_in(n, 16, 1024)) return "";
+  ctx->desc = sched_line(n, schedule_for(ctx, n));
+  return ctx->desc.c_str();
+}
+
+int tacaw_load_tuning(tacaw_ctx* ctx, const char* path) {
+  return guarded([&] {
+    if (!ctx || !path) fail(TACAW_E_ARG, "null argument");
+    std::ifstream f(path);
+    if (!f) return;
+    // one entry per line: {"arch": "gfx950", "n": 512, "row": 0, "col": 0, "C": 16}
+    std::string line;
+    while (std::getline(f, line)) {
+      if (line.find("\"n\"") == std::string::npos) continue;
+      auto num = [&](const char* k) -> int {
+        auto p = line.find(std::string("\"") + k + "\"");
+        if (p == std::string::npos) fail(TACAW_E_ARG, std::string("tuning line lacks ") + k);
+        p = line.find(':', p);
+        return std::atoi(line.c_str() + p + 1);
+      };
+      int n = num("n");
+      Sched s;
+      s.row_plan = num("row");
+      s.col_plan = num("col");
+      s.C = num("C");
+      if (!pow2_in(n, 16, 1024) || s.row_plan < 0 || s.row_plan >= n_plans(n) || s.col_plan < 0 ||
+          s.col_plan >= n_plans(n) || s.C < 1)
+        fail(TACAW_E_ARG, "malformed tuning entry");
+      ctx->sched[n] = s;
+    }
+  });
+}
+
+int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache_path,
+                   void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    if (!pow2_in(n, 16, 1024)) fail(TACAW_E_SIZE, "grid must be a power of two in [16, 1024]");
+    if (n_waves < 1) fail(TACAW_E_ARG, "n_waves must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t img = (size_t)n * n;
+    const int S = 4;
+    float* V = (float*)workspace(ctx, "tune_v", img * S * n_waves * sizeof(float));
+    float2* W = (float2*)workspace(ctx, "tune_w", img * n_waves * sizeof(float2));
+    hip_check(launch_zero(V, img * S * n_waves * sizeof(float), st), "zero");
+    hip_check(launch_zero(W, img * n_waves * sizeof(float2), st), "zero");
+    std::vector<double> dz(S, 2.0);
+    tacaw_specimen sp{n, n, n * 0.25, n * 0.25, S, dz.data(), 0.0, 2.0 / 3.0};
+    tacaw_beam bm{100e3, TACAW_PLANE_WAVE, 0, 0, 0, 1, nullptr};
+    tacaw_ms_job job{&sp, &bm, n_waves, V, (tacaw_c64*)W, nullptr};
+    MsBuild b = build_ms(ctx, 1, &job, 0, st, false, nullptr, nullptr);
+    b.jobs_dev = upload_vec(ctx, b.jobs, st, "jobs");
+    const ClassPlan& cp = b.classes[0];
+    int2* groups = upload_vec(ctx, cp.groups, st, "groups");
+    int4* waves = upload_vec(ctx, cp.waves, st, "waves");
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    Launcher L{ctx, st};
+    auto time_it = [&](auto&& fn) {
+      fn();   // warm-up
+      hip_check(hipEventRecord(e0, st), "hipEventRecord");
+      for (int r = 0; r < 5; ++r) fn();
+      hip_check(hipEventRecord(e1, st), "hipEventRecord");
+      hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      return ms;
+    };
+    Sched best = schedule_for(ctx, n);
+    float best_row = 1e30f, best_col = 1e30f;
+    for (int rp = 0; rp < n_plans(n); ++rp) {
+      Sched sc = best;
+      sc.row_plan = rp;
+      float ms = time_it([&] {
+        RowArgs ra{};
+        ra.jobs = b.jobs_dev;
+        ra.groups = groups;
+        ra.n_groups = (int)cp.groups.size();
+        ra.s = 1;
+        ra.in_buf = BUF_W;
+        ra.out_buf = BUF_W;
+        ra.stash_slot = -1;
+        ra.write_out = 1;
+        ra.ny = n;
+        L.row(n, sc, false, ra);
+      });
+      if (ms < best_row) { best_row = ms; best.row_plan = rp; }
+    }
+    for (int cpn = 0; cpn < n_plans(n); ++cpn)
+      for (int C = 8; C <= 64; C *= 2) {
+        if (C > n || col_lds_bytes(n, cpn, C) > ctx->max_lds) continue;
+        Sched sc = best;
+        sc.col_plan = cpn;
+        sc.C = C;
+        float ms = time_it([&] {
+          ColArgs ca{};
+          ca.jobs = b.jobs_dev;
+          ca.waves = waves;
+          ca.n_waves = (int)cp.waves.size();
+          ca.s = 1;
+          ca.in_buf = BUF_W;
+          ca.out_buf = BUF_W;
+          ca.C = C;
+          ca.nx = n;
+          ca.scale = 1.0f / (float)img;
+          L.col(n, sc, true, true, ca);
+        });
+        if (ms < best_col) { best_col = ms; best.col_plan = cpn; best.C = C; }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->sched[n] = best;
+    if (cache_path) {
+      std::map<int, Sched> all;
+      {
+        std::ifstream f(cache_path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+          auto p = line.find("\"n\"");
+          if (p == std::string::npos) continue;
+          auto num = [&](const char* k) {
+            auto q = line.find(std::string("\"") + k + "\"");
+            q = line.find(':', q);
+            return std::atoi(line.c_str() + q + 1);
+          };
+          Sched s;
+          s.row_plan = num("row");
+          s.col_plan = num("col");
+          s.C = num("C");
+          all[num("n")] = s;
+        }
+      }
+      all[n] = best;
+      std::ofstream o(cache_path);
+      for (auto& kv : all)
+        o << "{\"arch\": \"gfx950\", \"n\": " << kv.first << ", \"row\": " << kv.second.row_plan
+          << ", \"col\": " << kv.second.col_plan << ", \"C\": " << kv.second.C << "}\n";
+    }
+  });
+}
+
+}  // extern "C"

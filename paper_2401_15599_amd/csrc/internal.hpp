@@ -1,0 +1,134 @@
+// Internal declarations shared by the kernels and the host library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plans.hpp"
+
+namespace tacaw {
+
+constexpr int kWaves = 4;              // wavefronts per workgroup in every FFT kernel
+constexpr int kThreads = 64 * kWaves;
+constexpr int kMaxSpecies = 8;
+
+// Per-job view used by the multislice kernels (device memory; built by the host per call).
+struct MsJobDev {
+  const float* V;          // [T][S][ny][nx]
+  float2* W;               // [T][P][ny][nx]   forward working buffer / exit waves
+  float2* ckpt;            // [T][P][nck][ny][nx] or null
+  const float2* px;        // [S][nx] exp(-i pi lambda dz_s kx^2)
+  const float2* py;        // [S][ny] exp(-i pi lambda dz_s ky^2)
+  const int* nmax;         // [nx] band limit: column m keeps signed ky index n with |n| <= nmax[m]
+  const int* nap;          // [nx] probe aperture, same convention
+  const double* pxy;       // [P][2] probe positions
+  float2* adj;             // [T][P][ny][nx] adjoint state
+  float2* rec;             // [T][P][ny][nx] forward recompute buffer
+  float2* stash;           // [T][P][K][ny][nx] pre-transmission real-space waves of one segment
+  const float2* gexit;     // [T][P][ny][nx]
+  float* gV;               // [T][S][ny][nx]
+  int T, P, S, nx, ny;
+  int ck_stride, n_ck, stash_k;
+  float sigma;
+  float scale_mid, scale_last, scale_probe;
+  double lx, ly, lambda, defocus, cs;
+};
+
+enum Buf : int { BUF_W = 0, BUF_REC = 1, BUF_ADJ = 2, BUF_GEXIT = 3, BUF_CKPT = 4 };
+
+__host__ __device__ inline size_t img_off(int wave, int nx, int ny) {
+  return (size_t)wave * (size_t)nx * (size_t)ny;
+}
+
+struct RowArgs {
+  const MsJobDev* jobs;
+  const int2* groups;      // (job, t), sorted by S descending
+  int n_groups;            // active prefix
+  int s;                   // slice
+  int in_buf, out_buf;     // Buf codes; BUF_CKPT as input reads checkpoint s / ck_stride
+  int store_ckpt;          // forward: store the input row to the checkpoint of slice s
+  int stash_slot;          // >= 0: store psi_s (real space) into stash slot
+  int write_out;           // 0: skip the forward x-transform and the store
+  int ny;                  // rows per image (all jobs of a launch share nx, ny)
+};
+
+struct ColArgs {
+  const MsJobDev* jobs;
+  const int4* waves;       // (job, t, p, -), sorted by S descending
+  int n_waves;             // active prefix
+  int s;                   // slice whose propagator is applied
+  int in_buf, out_buf;
+  int conj_prop;           // apply conj(M P_s) (adjoint) instead of M P_s
+  int C;                   // columns per tile
+  float scale;             // 1/(nx ny), 1/sqrt(nx ny), ...
+  int nx;                  // columns per image (all jobs of a launch share nx, ny)
+};
+
+// plain batched 2-D transforms of contiguous images (potential build, position gradient)
+struct PlainArgs {
+  const void* in;
+  void* out;
+  int n_img, nx, ny, C;
+};
+
+// -------- launchers (defined in the .hip files) --------
+int n_plans(int n);
+const char* plan_name(int n, int idx);
+hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hipStream_t st);
+hipError_t launch_col(int n, int plan, bool dofwd, bool doinv, const ColArgs& a, int grid,
+                      hipStream_t st);
+hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStream_t st);
+hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st);
+int row_lines_per_wave(int n, int plan);
+int col_lds_bytes(int n, int plan, int C);
+
+// potentials
+hipError_t launch_bin_atoms(const float* xyz, const int* species, int n_snap, int n_atoms,
+                            int n_species, const double* bounds, int S, int* offsets, int* order,
+                            int* n_out, hipStream_t st);
+struct SfArgs {
+  const float* xyz; const int* order; const int* offsets; const float* ff;  // ff: [nsp][12] f32
+  float2* vk;              // [maps][ny][nx]
+  int t0, s_count, n_atoms, n_species, nx, ny;  // maps = (t0 + i / S, i % S)
+  double lx, ly;
+  float pref;              // 2 pi a0 e / (Lx Ly)
+  float kmax2;             // band limit in (1/A)^2 for |k|^2 (float comparison only for tile skip)
+  const int* nmax;         // [nx] exact band-limit table
+  int n_maps;
+};
+hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st);
+hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hipStream_t st);
+hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, hipStream_t st);
+struct PgArgs {
+  const float* xyz; const int* order; const int* offsets; const float* ff;
+  const float2* gk;        // [maps][ny][nx] DFT of dL/dV
+  float* gxy;              // [T][N][2]
+  int t0, s_count, n_atoms, n_species, nx, ny, n_maps;
+  double lx, ly;
+  float pref;
+  const int* nmax;
+};
+hipError_t launch_position_grad(const PgArgs& a, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// spectrum
+struct SpecArgs {
+  const float2* exit;      // [T][P][nq]
+  float* P;                // [n_e][nq]
+  int T, Pn, nq, n_e, hop, G, accumulate, Qt;
+};
+hipError_t launch_periodogram(const SpecArgs& a, hipStream_t st);
+struct FinArgs {
+  const float* P; const float* K;   // K: [n_e] DFT order
+  float* S; double* partial; double* norm;
+  int n_e, nx, ny, nqx, nqy, n_part;
+};
+hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
+struct SpecBwdArgs {
+  const float2* exit; const float* S; const double* norm; const float* gS; const float* K;
+  float2* gexit; double* partial;
+  int T, Pn, nx, ny, nq, n_e, hop, G, nqx, nqy, Qt, n_part;
+};
+hipError_t launch_spectrum_backward(const SpecBwdArgs& a, hipStream_t st);
+
+}  // namespace tacaw

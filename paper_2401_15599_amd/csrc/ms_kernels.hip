@@ -1,0 +1,496 @@
+// Multislice slice-step kernels: the x pass (row kernel) and the y pass (column kernel).
+//
+// A slice step psi <- F^-1[M P_s F[t_s psi]] is split at the 2-D transform's two axes.  Between
+// launches a wave is stored in the (kx, y) representation W = F_x[psi] / nx:
+//   row kernel, slice s:  psi = G_x W (x inverse transform), u = t_s psi, W' = F_x u
+//   column kernel, s:     W = G_y[ M P_s F_y W' ] / (nx ny)   (or, after the last slice, the exit
+//                         wave phi = M P_s F_y W' / sqrt(nx ny) stored in (kx, ky))
+// with F/G the unnormalised forward/inverse DFTs.  Each pass reads and writes the wave once (plus V
+// in the row pass), so one slice step moves 36 N^2 bytes through HBM.
+//
+// Row kernel: one line = one image row, held by L lanes of a wave; lines never share LDS, so the
+// transform needs no workgroup barrier.  All probe positions of a snapshot share one load of the V
+// row and one evaluation of exp(i sigma V).  Column kernel: a workgroup stages C columns x N rows
+// through LDS with coalesced row segments, each wave transforms whole columns in place in that
+// tile, and the tile is written back with coalesced stores.
+#include "internal.hpp"
+
+namespace tacaw {
+
+template <class F> static bool with_plan(int n, int idx, F&& f) {
+  switch (n) {
+    case 16: if (idx == 1) f(P16b{}); else f(P16a{}); return true;
+    case 32: if (idx == 1) f(P32b{}); else f(P32a{}); return true;
+    case 64: if (idx == 1) f(P64b{}); else f(P64a{}); return true;
+    case 128: if (idx == 1) f(P128b{}); else f(P128a{}); return true;
+    case 256: if (idx == 1) f(P256b{}); else if (idx == 2) f(P256c{}); else f(P256a{}); return true;
+    case 512: if (idx == 1) f(P512b{}); else f(P512a{}); return true;
+    case 1024: if (idx == 1) f(P1024b{}); else f(P1024a{}); return true;
+    default: return false;
+  }
+}
+
+int n_plans(int n) {
+  switch (n) {
+    case 16: case 32: case 64: case 128: case 512: case 1024: return 2;
+    case 256: return 3;
+    default: return 0;
+  }
+}
+
+const char* plan_name(int n, int idx) {
+  static const char* names[] = {"16:L2:8x2", "16:L4:4x4", "32:L4:8x4", "32:L2:16x2", "64:L8:8x8",
+                                "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "256:L32:8x8x4",
+                                "256:L16:16x16", "256:L64:4x4x4x4", "512:L64:8x8x8",
+                                "512:L32:16x8x4", "1024:L64:16x16x4", "1024:L64:16x4x16"};
+  int base = 0;
+  switch (n) {
+    case 16: base = 0; break; case 32: base = 2; break; case 64: base = 4; break;
+    case 128: base = 6; break; case 256: base = 8; break; case 512: base = 11; break;
+    case 1024: base = 13; break; default: return "?";
+  }
+  if (idx < 0 || idx >= n_plans(n)) return "?";
+  return names[base + idx];
+}
+
+__device__ __forceinline__ float2* pick_buf(const MsJobDev& J, int code, int wave, int s) {
+  size_t o = img_off(wave, J.nx, J.ny);
+  switch (code) {
+    case BUF_W: return J.W + o;
+    case BUF_REC: return J.rec + o;
+    case BUF_ADJ: return J.adj + o;
+    case BUF_GEXIT: return const_cast<float2*>(J.gexit) + o;
+    default: return J.ckpt + img_off(wave * J.n_ck + s / J.ck_stride, J.nx, J.ny);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// x pass
+template <class P, bool ADJ>
+__global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES;
+  __shared__ float2 lds_all[kWaves * LINES * P::LDS_LINE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int line = lane / L, l = lane % L;
+  float2* lds = lds_all + (wave * LINES + line) * P::LDS_LINE;
+  float2 tw[P::NTW];
+  PlanOps<P>::twiddles(tw, l);
+
+  const int ny = a.ny;
+  const long n_tasks = (long)a.n_groups * ny;
+  const long stride = (long)gridDim.x * kWaves * LINES;
+  for (long base = ((long)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
+    const long task = base + line;
+    if (task >= n_tasks) continue;
+    const int g = (int)(task / ny), y = (int)(task % ny);
+    const int2 gr = a.groups[g];
+    const MsJobDev& J = a.jobs[gr.x];
+    const int t = gr.y, s = a.s;
+    const size_t row = (size_t)y * N;
+    const float* vrow = J.V + ((size_t)(t * J.S + s) * ny) * N + row;
+    float2 tr[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      float sn, cs;
+      sincosf(J.sigma * vrow[l + L * j], &sn, &cs);
+      tr[j] = make_float2(cs, sn);
+    }
+    float gacc[ADJ ? E : 1];
+    if constexpr (ADJ) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) gacc[j] = 0.f;
+    }
+    for (int p = 0; p < J.P; ++p) {
+      const int w = t * J.P + p;
+      const float2* in = pick_buf(J, a.in_buf, w, s) + row;
+      float2 v[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = in[l + L * j];
+      if (!ADJ && a.store_ckpt) {
+        float2* ck = J.ckpt + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
+#pragma unroll
+        for (int j = 0; j < E; ++j) ck[l + L * j] = v[j];
+      }
+      FFT<P>::template run<true>(v, tw, lds, l);          // psi_s (real space)
+      if constexpr (!ADJ) {
+        if (a.stash_slot >= 0) {
+          float2* st = J.stash + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
+#pragma unroll
+          for (int j = 0; j < E; ++j) st[l + L * j] = v[j];
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = cmul(v[j], tr[j]);
+      } else {
+        // v = chi_s (adjoint at the post-transmission point); psi_s from the stash
+        const float2* st = J.stash + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          float2 tp = cmul(tr[j], st[l + L * j]);
+          gacc[j] -= J.sigma * (v[j].x * tp.y - v[j].y * tp.x);   // -sigma Im(conj(chi) t psi)
+          v[j] = cmulc(v[j], tr[j]);                               // conj(t) chi
+        }
+      }
+      if (a.write_out) {
+        FFT<P>::template run<false>(v, tw, lds, l);
+        float2* out = pick_buf(J, a.out_buf, w, s) + row;
+#pragma unroll
+        for (int j = 0; j < E; ++j) out[l + L * j] = v[j];
+      }
+    }
+    if constexpr (ADJ) {
+      float* grow = J.gV + ((size_t)(t * J.S + s) * ny) * N + row;
+#pragma unroll
+      for (int j = 0; j < E; ++j) grow[l + L * j] = gacc[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// y pass: optional forward y transform, propagator, optional inverse y transform
+template <class P, bool DOFWD, bool DOINV>
+__global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE;
+  extern __shared__ float2 tile[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int line = lane / L, l = lane % L;
+  float2 tw[P::NTW];
+  PlanOps<P>::twiddles(tw, l);
+  const int C = a.C, nx = a.nx;
+  const int tpi = nx / C;
+  const long n_tasks = (long)a.n_waves * tpi;
+  for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    const int4 wv = a.waves[task / tpi];
+    const int col0 = (int)(task % tpi) * C;
+    const MsJobDev& J = a.jobs[wv.x];
+    const int w = wv.y * J.P + wv.z, s = a.s;
+    const float2* in = pick_buf(J, a.in_buf, w, s);
+    float2* out = pick_buf(J, a.out_buf, w, s);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
+      int c = idx % C, r = idx / C;
+      tile[c * CS + lds_pad(r)] = in[(size_t)r * nx + col0 + c];
+    }
+    __syncthreads();
+    for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
+      const int c = cb + line;
+      if (c < C) {
+        float2* lds = tile + c * CS;
+        float2 v[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
+        if constexpr (DOFWD) FFT<P>::template run<false>(v, tw, lds, l);
+        const int m = col0 + c;
+        const int nm = J.nmax[m];
+        const float2 pxm = J.px[(size_t)s * nx + m];
+        const float2* pys = J.py + (size_t)s * N;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const int n = l + L * j;
+          const int ns = n < N / 2 ? n : n - N;
+          float2 d = make_float2(0.f, 0.f);
+          if ((ns < 0 ? -ns : ns) <= nm) d = cmul(pxm, pys[n]);
+          if (a.conj_prop) d.y = -d.y;
+          v[j] = cscale(cmul(v[j], d), a.scale);
+        }
+        if constexpr (DOINV) FFT<P>::template run<true>(v, tw, lds, l);
+#pragma unroll
+        for (int j = 0; j < E; ++j) lds[lds_pad(l + L * j)] = v[j];
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
+      int c = idx % C, r = idx / C;
+      out[(size_t)r * nx + col0 + c] = tile[c * CS + lds_pad(r)];
+    }
+  }
+}
+
+// probe: psi_0 in the (kx, y) representation, W = G_y[a(k)] / (sqrt(nx ny) sqrt(n_aperture))
+template <class P>
+__global__ __launch_bounds__(kThreads) void k_probe_init(ColArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE;
+  extern __shared__ float2 tile[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int line = lane / L, l = lane % L;
+  float2 tw[P::NTW];
+  PlanOps<P>::twiddles(tw, l);
+  const int C = a.C, nx = a.nx;
+  const int tpi = nx / C;
+  const long n_tasks = (long)a.n_waves * tpi;
+  for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    const int4 wv = a.waves[task / tpi];
+    const int col0 = (int)(task % tpi) * C;
+    const MsJobDev& J = a.jobs[wv.x];
+    const int w = wv.y * J.P + wv.z;
+    float2* out = pick_buf(J, a.out_buf, w, 0);
+    const double xp = J.pxy[2 * wv.z], yp = J.pxy[2 * wv.z + 1];
+    __syncthreads();
+    for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
+      const int c = cb + line;
+      if (c < C) {
+        float2* lds = tile + c * CS;
+        const int m = col0 + c;
+        const int ms = m < nx / 2 ? m : m - nx;
+        const int na = J.nap[m];
+        const double kx = (double)ms / J.lx;
+        float2 v[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const int n = l + L * j;
+          const int ns = n < N / 2 ? n : n - N;
+          v[j] = make_float2(0.f, 0.f);
+          if ((ns < 0 ? -ns : ns) <= na) {
+            const double ky = (double)ns / J.ly;
+            const double k2 = kx * kx + ky * ky;
+            const double chi = M_PI * J.lambda * J.defocus * k2 +
+                               0.5 * M_PI * J.cs * J.lambda * J.lambda * J.lambda * k2 * k2;
+            double cyc = chi / (2.0 * M_PI) + kx * xp + ky * yp;
+            cyc -= floor(cyc);
+            double sn, cs;
+            sincos(-2.0 * M_PI * cyc, &sn, &cs);
+            v[j] = make_float2((float)cs, (float)sn);
+          }
+        }
+        FFT<P>::template run<true>(v, tw, lds, l);
+#pragma unroll
+        for (int j = 0; j < E; ++j) lds[lds_pad(l + L * j)] = cscale(v[j], J.scale_probe);
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
+      int c = idx % C, r = idx / C;
+      out[(size_t)r * nx + col0 + c] = tile[c * CS + lds_pad(r)];
+    }
+  }
+}
+
+// plane wave: W(kx, y) = delta_{kx,0} / sqrt(nx ny)
+__global__ __launch_bounds__(kThreads) void k_plane_init(ColArgs a) {
+  const int nx = a.nx;
+  for (long wi = blockIdx.x; wi < a.n_waves; wi += gridDim.x) {
+    const int4 wv = a.waves[wi];
+    const MsJobDev& J = a.jobs[wv.x];
+    const int w = wv.y * J.P + wv.z;
+    float2* out = pick_buf(J, a.out_buf, w, 0);
+    const size_t n = (size_t)nx * J.ny;
+    for (size_t i = threadIdx.x; i < n; i += kThreads)
+      out[i] = make_float2((i % nx) == 0 ? J.scale_last : 0.f, 0.f);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// plain batched 2-D transforms of contiguous images
+template <class P, bool INV, bool REAL_IN, bool REAL_OUT>
+__global__ __launch_bounds__(kThreads) void k_row_plain(PlainArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES;
+  __shared__ float2 lds_all[kWaves * LINES * P::LDS_LINE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int line = lane / L, l = lane % L;
+  float2* lds = lds_all + (wave * LINES + line) * P::LDS_LINE;
+  float2 tw[P::NTW];
+  PlanOps<P>::twiddles(tw, l);
+  const long n_tasks = (long)a.n_img * a.ny;
+  const long stride = (long)gridDim.x * kWaves * LINES;
+  for (long base = ((long)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
+    const long task = base + line;
+    if (task >= n_tasks) continue;
+    const size_t off = (size_t)task * N;
+    float2 v[E];
+    if constexpr (REAL_IN) {
+      const float* in = (const float*)a.in + off;
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = make_float2(in[l + L * j], 0.f);
+    } else {
+      const float2* in = (const float2*)a.in + off;
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = in[l + L * j];
+    }
+    FFT<P>::template run<INV>(v, tw, lds, l);
+    if constexpr (REAL_OUT) {
+      float* out = (float*)a.out + off;
+#pragma unroll
+      for (int j = 0; j < E; ++j) out[l + L * j] = v[j].x;
+    } else {
+      float2* out = (float2*)a.out + off;
+#pragma unroll
+      for (int j = 0; j < E; ++j) out[l + L * j] = v[j];
+    }
+  }
+}
+
+template <class P, bool INV>
+__global__ __launch_bounds__(kThreads) void k_col_plain(PlainArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE;
+  extern __shared__ float2 tile[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int line = lane / L, l = lane % L;
+  float2 tw[P::NTW];
+  PlanOps<P>::twiddles(tw, l);
+  const int C = a.C, nx = a.nx;
+  const int tpi = nx / C;
+  const long n_tasks = (long)a.n_img * tpi;
+  for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    const size_t ioff = (size_t)(task / tpi) * nx * N;
+    const int col0 = (int)(task % tpi) * C;
+    const float2* in = (const float2*)a.in + ioff;
+    float2* out = (float2*)a.out + ioff;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
+      int c = idx % C, r = idx / C;
+      tile[c * CS + lds_pad(r)] = in[(size_t)r * nx + col0 + c];
+    }
+    __syncthreads();
+    for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
+      const int c = cb + line;
+      if (c < C) {
+        float2* lds = tile + c * CS;
+        float2 v[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
+        FFT<P>::template run<INV>(v, tw, lds, l);
+#pragma unroll
+        for (int j = 0; j < E; ++j) lds[lds_pad(l + L * j)] = v[j];
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
+      int c = idx % C, r = idx / C;
+      out[(size_t)r * nx + col0 + c] = tile[c * CS + lds_pad(r)];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// launchers
+
+int row_lines_per_wave(int n, int plan) {
+  int lines = 0;
+  with_plan(n, plan, [&](auto p) { lines = decltype(p)::LINES; });
+  return lines;
+}
+
+int col_lds_bytes(int n, int plan, int C) {
+  int b = 0;
+  with_plan(n, plan, [&](auto p) { b = C * decltype(p)::LDS_LINE * (int)sizeof(float2); });
+  return b;
+}
+
+hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hipStream_t st) {
+  hipError_t e = hipErrorInvalidValue;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    if (adj) hipLaunchKernelGGL((k_row<P, true>), dim3(grid), dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_row<P, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    e = hipGetLastError();
+  });
+  return e;
+}
+
+// Dynamic LDS limits are raised once per context creation (never during graph capture).
+void prepare_dynamic_lds(int max_bytes) {
+  for (int n = 16; n <= 1024; n *= 2)
+    for (int idx = 0; idx < n_plans(n); ++idx)
+      with_plan(n, idx, [&](auto p) {
+        using P = decltype(p);
+        const int attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+        (void)hipFuncSetAttribute((const void*)k_col<P, true, true>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_col<P, true, false>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_col<P, false, true>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_probe_init<P>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_col_plain<P, true>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_col_plain<P, false>, (hipFuncAttribute)attr, max_bytes);
+      });
+  (void)hipGetLastError();
+}
+
+hipError_t launch_col(int n, int plan, bool dofwd, bool doinv, const ColArgs& a, int grid,
+                      hipStream_t st) {
+  hipError_t e = hipErrorInvalidValue;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
+    if (dofwd && doinv)
+      hipLaunchKernelGGL((k_col<P, true, true>), dim3(grid), dim3(kThreads), lds, st, a);
+    else if (dofwd)
+      hipLaunchKernelGGL((k_col<P, true, false>), dim3(grid), dim3(kThreads), lds, st, a);
+    else
+      hipLaunchKernelGGL((k_col<P, false, true>), dim3(grid), dim3(kThreads), lds, st, a);
+    e = hipGetLastError();
+  });
+  return e;
+}
+
+hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStream_t st) {
+  hipError_t e = hipErrorInvalidValue;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
+    hipLaunchKernelGGL((k_probe_init<P>), dim3(grid), dim3(kThreads), lds, st, a);
+    e = hipGetLastError();
+  });
+  return e;
+}
+
+hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_init, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+static int plain_cols(int nx, int n) {
+  int c = (n <= 64) ? 64 : (n <= 256 ? 32 : 16);
+  if (n == 1024) c = 8;
+  return c > nx ? nx : c;
+}
+
+hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hipStream_t st) {
+  if (n_img <= 0) return hipSuccess;
+  hipError_t e = hipErrorInvalidValue;
+  PlainArgs a{vk, vk, n_img, nx, ny, plain_cols(nx, ny)};
+  with_plan(ny, 0, [&](auto p) {
+    using P = decltype(p);
+    const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
+    long tasks = (long)n_img * (nx / a.C);
+    int grid = (int)(tasks < 4096 ? tasks : 4096);
+    hipLaunchKernelGGL((k_col_plain<P, true>), dim3(grid), dim3(kThreads), lds, st, a);
+    e = hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  PlainArgs b{vk, V, n_img, nx, ny, 0};
+  with_plan(nx, 0, [&](auto p) {
+    using P = decltype(p);
+    long tasks = (long)n_img * ny;
+    long g = (tasks + kWaves * P::LINES - 1) / (kWaves * P::LINES);
+    int grid = (int)(g < 4096 ? g : 4096);
+    hipLaunchKernelGGL((k_row_plain<P, true, false, true>), dim3(grid), dim3(kThreads), 0, st, b);
+    e = hipGetLastError();
+  });
+  return e;
+}
+
+hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img,
+                            hipStream_t st) {
+  if (n_img <= 0) return hipSuccess;
+  hipError_t e = hipErrorInvalidValue;
+  PlainArgs b{g, gk, n_img, nx, ny, 0};
+  with_plan(nx, 0, [&](auto p) {
+    using P = decltype(p);
+    long tasks = (long)n_img * ny;
+    long gg = (tasks + kWaves * P::LINES - 1) / (kWaves * P::LINES);
+    int grid = (int)(gg < 4096 ? gg : 4096);
+    hipLaunchKernelGGL((k_row_plain<P, false, true, false>), dim3(grid), dim3(kThreads), 0, st, b);
+    e = hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  PlainArgs a{gk, gk, n_img, nx, ny, plain_cols(nx, ny)};
+  with_plan(ny, 0, [&](auto p) {
+    using P = decltype(p);
+    const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
+    long tasks = (long)n_img * (nx / a.C);
+    int grid = (int)(tasks < 4096 ? tasks : 4096);
+    hipLaunchKernelGGL((k_col_plain<P, false>), dim3(grid), dim3(kThreads), lds, st, a);
+    e = hipGetLastError();
+  });
+  return e;
+}
+
+}  // namespace tacaw

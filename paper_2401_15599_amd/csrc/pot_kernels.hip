@@ -1,0 +1,447 @@
+// Slice binning, projected slice potentials and their adjoint with respect to atom positions.
+//
+// V_s(k) = pref M(k) sum_Z f_Z(|k|) sum_{j in (s, Z)} exp(-2 pi i kx x_j) exp(-2 pi i ky y_j)
+// The phase factorises into an x table and a y table per atom, so each 64 x 64 tile of k-space is a
+// small complex outer-product accumulation over the atoms of a slice (a GEMM-like contraction done
+// on the vector ALUs from LDS-staged phase tables).  Phases use exact argument reduction: the
+// fractional coordinate x/Lx is rounded to a 32-bit fixed-point number U, and the phase of index m
+// is the wrapped integer product m*U (units of 2^-32 turns), so no large float argument ever
+// reaches the sine/cosine.  Tiles outside the band limit are written as zeros without any work.
+#include "internal.hpp"
+
+namespace tacaw {
+
+// ---------------------------------------------------------------------------------------------
+// binning: one workgroup per snapshot, stable counting sort by key = slice * n_species + species
+constexpr int kBinThreads = 256;
+
+__device__ __forceinline__ int slice_of(float zf, const double* b, int S) {
+  const double z = (double)zf;
+  if (!(z >= b[0]) || !(z < b[S])) return -1;
+  int lo = 0, hi = S;            // b[lo] <= z < b[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (b[mid] <= z) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin(const float* xyz, const int* species,
+                                                     int n_atoms, int nsp, const double* bounds,
+                                                     int S, int* offsets, int* order, int* n_out) {
+  extern __shared__ int sh[];
+  const int K = S * nsp;
+  int* cnt = sh;                       // [K] counts, then running cursors
+  int* keys = sh + K;                  // [256] keys of the current chunk
+  int* part = keys + kBinThreads;      // [256] scan partials / outside counts
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const float* X = xyz + (size_t)t * n_atoms * 3;
+  for (int i = tid; i < K; i += kBinThreads) cnt[i] = 0;
+  __syncthreads();
+  int outside = 0;
+  for (int j = tid; j < n_atoms; j += kBinThreads) {
+    int s = slice_of(X[3 * j + 2], bounds, S);
+    if (s < 0) { ++outside; continue; }
+    atomicAdd(&cnt[s * nsp + species[j]], 1);
+  }
+  part[tid] = outside;
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int i = 0; i < kBinThreads; ++i) tot += part[i];
+    if (n_out) n_out[t] = tot;
+  }
+  __syncthreads();
+  // exclusive scan of cnt: each thread owns a contiguous range
+  const int per = (K + kBinThreads - 1) / kBinThreads;
+  const int a0 = tid * per, a1 = min(K, a0 + per);
+  int local = 0;
+  for (int i = a0; i < a1; ++i) local += cnt[i];
+  part[tid] = local;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < kBinThreads; ++i) { int v = part[i]; part[i] = run; run += v; }
+  }
+  __syncthreads();
+  int run = part[tid];
+  int* off = offsets + (size_t)t * (K + 1);
+  for (int i = a0; i < a1; ++i) { int v = cnt[i]; cnt[i] = run; off[i] = run; run += v; }
+  if (tid == kBinThreads - 1) off[K] = part[tid] + local;
+  __syncthreads();
+  // stable scatter in chunks of 256 atoms
+  int* ord = order + (size_t)t * n_atoms;
+  for (int base = 0; base < n_atoms; base += kBinThreads) {
+    const int j = base + tid;
+    int key = -1;
+    if (j < n_atoms) {
+      int s = slice_of(X[3 * j + 2], bounds, S);
+      if (s >= 0) key = s * nsp + species[j];
+    }
+    keys[tid] = key;
+    __syncthreads();
+    int rank = 0, last = 1;
+    if (key >= 0) {
+      for (int i = 0; i < tid; ++i) rank += (keys[i] == key);
+      for (int i = tid + 1; i < kBinThreads; ++i)
+        if (keys[i] == key) { last = 0; break; }
+      ord[cnt[key] + rank] = j;
+    }
+    __syncthreads();
+    if (key >= 0 && last) cnt[key] += rank + 1;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_bin_atoms(const float* xyz, const int* species, int n_snap, int n_atoms,
+                            int n_species, const double* bounds, int S, int* offsets, int* order,
+                            int* n_out, hipStream_t st) {
+  const int K = S * n_species;
+  const int lds = (K + 2 * kBinThreads) * (int)sizeof(int);
+  hipFuncSetAttribute((const void*)k_bin, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipLaunchKernelGGL(k_bin, dim3(n_snap), dim3(kBinThreads), lds, st, xyz, species, n_atoms,
+                     n_species, bounds, S, offsets, order, n_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// phase tables
+__device__ __forceinline__ unsigned frac_fixed(float x, double len) {
+  double u = (double)x / len;
+  u -= floor(u);
+  long long q = llrint(u * 4294967296.0);
+  return (unsigned)(q & 0xffffffffLL);
+}
+
+// exp(-2 pi i m U / 2^32) for signed index m
+__device__ __forceinline__ float2 phase_factor(int m, unsigned U) {
+  unsigned ph = (unsigned)m * U;
+  float half_turns = (float)(int)ph * 4.656612873077393e-10f;   // * 2^-31
+  float s, c;
+  sincospif(half_turns, &s, &c);
+  return make_float2(c, -s);
+}
+
+__device__ __forceinline__ float form_factor(const float* f, float q2) {
+  return f[0] / (q2 + f[1]) + f[2] / (q2 + f[3]) + f[4] / (q2 + f[5]) +
+         f[6] * __expf(-f[7] * q2) + f[8] * __expf(-f[9] * q2) + f[10] * __expf(-f[11] * q2);
+}
+
+constexpr int kTile = 64;     // k-space tile edge (clamped to the grid)
+constexpr int kChunk = 64;    // atoms staged per LDS fill
+
+// one workgroup per (map, tile); 256 threads as 16 x 16, each owning 4 x 4 outputs
+__global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
+  __shared__ float2 ex[kChunk][kTile];
+  __shared__ float2 ey[kChunk][kTile];
+  __shared__ float ffs[kMaxSpecies * 12];
+  const int tx_n = (a.nx + kTile - 1) / kTile, ty_n = (a.ny + kTile - 1) / kTile;
+  const int tiles = tx_n * ty_n;
+  const int map = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  if (map >= a.n_maps) return;
+  const int TW = min(kTile, a.nx), TH = min(kTile, a.ny);
+  const int m0 = (tile % tx_n) * TW, n0 = (tile / tx_n) * TH;
+  const int t = a.t0 + map / a.s_count, s = map % a.s_count;
+  const int tid = threadIdx.x, txi = tid & 15, tyi = tid >> 4;
+  for (int i = tid; i < a.n_species * 12; i += 256) ffs[i] = a.ff[i];
+
+  // does any k of this tile pass the band limit?  (exact integer table)
+  int any = 0;
+  {
+    int minabs_n = 1 << 30;
+    for (int n = n0; n < n0 + TH; ++n) {
+      int ns = n < a.ny / 2 ? n : n - a.ny;
+      minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
+    }
+    for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
+  }
+  any = __syncthreads_or(any);
+  float2* out = a.vk + (size_t)map * a.nx * a.ny;
+  if (!any) {
+    for (int i = tid; i < TW * TH; i += 256)
+      out[(size_t)(n0 + i / TW) * a.nx + m0 + i % TW] = make_float2(0.f, 0.f);
+    return;
+  }
+
+  float2 vacc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) vacc[i][j] = make_float2(0.f, 0.f);
+
+  const float* X = a.xyz + (size_t)t * a.n_atoms * 3;
+  const int* off = a.offsets + (size_t)t * (a.s_count * a.n_species + 1);
+  const int* ord = a.order + (size_t)t * a.n_atoms;
+  for (int z = 0; z < a.n_species; ++z) {
+    const int j0 = off[s * a.n_species + z], j1 = off[s * a.n_species + z + 1];
+    if (j1 <= j0) continue;
+    float2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
+    for (int c0 = j0; c0 < j1; c0 += kChunk) {
+      const int na = min(kChunk, j1 - c0);
+      __syncthreads();
+      for (int i = tid; i < kChunk * kTile; i += 256) {
+        const int at = i / kTile, k = i % kTile;
+        float2 fx = make_float2(0.f, 0.f), fy = make_float2(0.f, 0.f);
+        if (at < na) {
+          const int aj = ord[c0 + at];
+          if (k < TW) {
+            const int m = m0 + k, ms = m < a.nx / 2 ? m : m - a.nx;
+            fx = phase_factor(ms, frac_fixed(X[3 * aj], a.lx));
+          }
+          if (k < TH) {
+            const int n = n0 + k, ns = n < a.ny / 2 ? n : n - a.ny;
+            fy = phase_factor(ns, frac_fixed(X[3 * aj + 1], a.ly));
+          }
+        }
+        ex[at][k] = fx;
+        ey[at][k] = fy;
+      }
+      __syncthreads();
+      for (int at = 0; at < na; ++at) {
+        float2 xv[4], yv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = ex[at][txi + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) yv[i] = ey[at][tyi + 16 * i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc[i][j].x = fmaf(yv[i].x, xv[j].x, fmaf(-yv[i].y, xv[j].y, acc[i][j].x));
+            acc[i][j].y = fmaf(yv[i].x, xv[j].y, fmaf(yv[i].y, xv[j].x, acc[i][j].y));
+          }
+      }
+    }
+    // multiply by the form factor of species z
+    const float* f = ffs + 12 * z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int n = n0 + tyi + 16 * i, ns = n < a.ny / 2 ? n : n - a.ny;
+      const float ky = (float)ns / (float)a.ly;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + txi + 16 * j, ms = m < a.nx / 2 ? m : m - a.nx;
+        const float kx = (float)ms / (float)a.lx;
+        const float fz = form_factor(f, kx * kx + ky * ky);
+        vacc[i][j].x = fmaf(fz, acc[i][j].x, vacc[i][j].x);
+        vacc[i][j].y = fmaf(fz, acc[i][j].y, vacc[i][j].y);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int ti = tyi + 16 * i;
+    if (ti >= TH) continue;
+    const int n = n0 + ti, ns = n < a.ny / 2 ? n : n - a.ny, an = ns < 0 ? -ns : ns;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int tj = txi + 16 * j;
+      if (tj >= TW) continue;
+      const int m = m0 + tj;
+      float2 v = (an <= a.nmax[m]) ? cscale(vacc[i][j], a.pref) : make_float2(0.f, 0.f);
+      out[(size_t)n * a.nx + m] = v;
+    }
+  }
+}
+
+hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
+  const int tx_n = (a.nx + kTile - 1) / kTile, ty_n = (a.ny + kTile - 1) / kTile;
+  const long blocks = (long)a.n_maps * tx_n * ty_n;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// dL/d(x, y): one workgroup per (map, species-pure chunk of 64 atoms); loops over k tiles.
+// H(k) = conj(G(k)) pref M(k) f_Z(|k|);  dx_j = 2 pi Im sum_n ey_j(n) sum_m H(n,m) kx_m ex_j(m)
+//                                        dy_j = 2 pi Im sum_n ey_j(n) ky_n sum_m H(n,m) ex_j(m)
+__global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chunks,
+                                                      const int* n_chunks) {
+  __shared__ float2 H[kTile][kTile + 1];
+  __shared__ float2 ex[kChunk][kTile + 1];
+  __shared__ float2 ey[kChunk][kTile + 1];
+  __shared__ float red[256][2];
+  if ((int)blockIdx.x >= *n_chunks) return;
+  const int4 ch = chunks[blockIdx.x];   // (map, first CSR index, count, species)
+  const int map = ch.x, c0 = ch.y, na = ch.z, z = ch.w;
+  const int t = a.t0 + map / a.s_count;
+  const int tid = threadIdx.x;
+  const int am = tid >> 2, nsub = tid & 3;   // atom within chunk, n subset (rows nsub + 4 i)
+  const float* X = a.xyz + (size_t)t * a.n_atoms * 3;
+  const int* ord = a.order + (size_t)t * a.n_atoms;
+  const float2* G = a.gk + (size_t)map * a.nx * a.ny;
+  float f[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) f[i] = a.ff[12 * z + i];
+  const int TW = min(kTile, a.nx), TH = min(kTile, a.ny);
+  const int tx_n = a.nx / TW, ty_n = a.ny / TH;
+  float dx = 0.f, dy = 0.f;
+  for (int ty = 0; ty < ty_n; ++ty) {
+    const int n0 = ty * TH;
+    int minabs_n = 1 << 30;
+    for (int n = n0; n < n0 + TH; ++n) {
+      int ns = n < a.ny / 2 ? n : n - a.ny;
+      minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
+    }
+    for (int tx = 0; tx < tx_n; ++tx) {
+      const int m0 = tx * TW;
+      int any = 0;
+      for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
+      if (!__syncthreads_or(any)) continue;
+      for (int i = tid; i < kTile * kTile; i += 256) {
+        const int r = i / kTile, c = i % kTile;
+        float2 h = make_float2(0.f, 0.f);
+        if (r < TH && c < TW) {
+          const int n = n0 + r, m = m0 + c;
+          const int ns = n < a.ny / 2 ? n : n - a.ny, ms = m < a.nx / 2 ? m : m - a.nx;
+          if ((ns < 0 ? -ns : ns) <= a.nmax[m]) {
+            const float ky = (float)ns / (float)a.ly, kx = (float)ms / (float)a.lx;
+            const float w = a.pref * form_factor(f, kx * kx + ky * ky);
+            const float2 g = G[(size_t)n * a.nx + m];
+            h = make_float2(g.x * w, -g.y * w);
+          }
+        }
+        H[r][c] = h;
+      }
+      for (int i = tid; i < kChunk * kTile; i += 256) {
+        const int at = i / kTile, k = i % kTile;
+        float2 fx = make_float2(0.f, 0.f), fy = make_float2(0.f, 0.f);
+        if (at < na) {
+          const int aj = ord[c0 + at];
+          if (k < TW) {
+            const int m = m0 + k, ms = m < a.nx / 2 ? m : m - a.nx;
+            fx = phase_factor(ms, frac_fixed(X[3 * aj], a.lx));
+          }
+          if (k < TH) {
+            const int n = n0 + k, ns = n < a.ny / 2 ? n : n - a.ny;
+            fy = phase_factor(ns, frac_fixed(X[3 * aj + 1], a.ly));
+          }
+        }
+        ex[at][k] = fx;
+        ey[at][k] = fy;
+      }
+      __syncthreads();
+      if (am < na) {
+        float2 U[16], Ux[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) { U[i] = make_float2(0.f, 0.f); Ux[i] = U[i]; }
+        for (int c = 0; c < TW; ++c) {
+          const int m = m0 + c, ms = m < a.nx / 2 ? m : m - a.nx;
+          const float kx = (float)ms / (float)a.lx;
+          const float2 e = ex[am][c];
+          const float2 ek = make_float2(e.x * kx, e.y * kx);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const float2 h = H[i * 4 + nsub][c];     // interleaved rows: no bank conflicts
+            U[i] = cadd(U[i], cmul(h, e));
+            Ux[i] = cadd(Ux[i], cmul(h, ek));
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int r = i * 4 + nsub;
+          if (r < TH) {
+            const int n = n0 + r, ns = n < a.ny / 2 ? n : n - a.ny;
+            const float ky = (float)ns / (float)a.ly;
+            const float2 e = ey[am][r];
+            dx += cmul(e, Ux[i]).y;
+            dy += ky * cmul(e, U[i]).y;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  red[tid][0] = dx;
+  red[tid][1] = dy;
+  __syncthreads();
+  if (nsub == 0 && am < na) {
+    float sx = 0.f, sy = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { sx += red[tid + k][0]; sy += red[tid + k][1]; }
+    const int aj = ord[c0 + am];
+    float* out = a.gxy + ((size_t)t * a.n_atoms + aj) * 2;
+    const float two_pi = 6.283185307179586f;
+    out[0] = two_pi * sx;
+    out[1] = two_pi * sy;
+  }
+}
+
+}  // namespace tacaw
+
+namespace tacaw {
+// Work list for the position gradient: species-pure chunks of at most 64 atoms per map, in map
+// order, built on the device from the CSR offsets (one workgroup, fixed order, no host sync).
+__global__ __launch_bounds__(256) void k_chunk_list(const int* offsets, int t0, int nt, int S,
+                                                   int nsp, int4* chunks, int cap, int* count) {
+  __shared__ int sc[256];
+  const int tid = threadIdx.x;
+  const int K = S * nsp, total = nt * K;
+  int running = 0;
+  for (int base = 0; base < total; base += 256) {
+    const int i = base + tid;
+    int nch = 0, start = 0, cnt = 0, map = 0, z = 0;
+    if (i < total) {
+      const int tl = i / K, key = i % K;
+      const int* off = offsets + (size_t)(t0 + tl) * (K + 1);
+      start = off[key];
+      cnt = off[key + 1] - start;
+      nch = (cnt + kChunk - 1) / kChunk;
+      map = tl * S + key / nsp;
+      z = key % nsp;
+    }
+    sc[tid] = nch;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {      // inclusive scan (Hillis-Steele)
+      int v = tid >= w ? sc[tid - w] : 0;
+      __syncthreads();
+      sc[tid] += v;
+      __syncthreads();
+    }
+    const int pos = running + sc[tid] - nch;
+    for (int k = 0; k < nch; ++k)
+      if (pos + k < cap)
+        chunks[pos + k] = make_int4(map, start + k * kChunk, min(kChunk, cnt - k * kChunk), z);
+    running += sc[255];
+    __syncthreads();
+  }
+  if (tid == 0) *count = running < cap ? running : cap;
+}
+
+hipError_t launch_chunk_list(const int* offsets, int t0, int nt, int S, int nsp, int4* chunks,
+                             int cap, int* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_chunk_list, dim3(1), dim3(256), 0, st, offsets, t0, nt, S, nsp, chunks, cap,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_position_grad_chunks(const PgArgs& a, const int4* chunks, int cap,
+                                       const int* count, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_position_grad, dim3(cap), dim3(256), 0, st, a, chunks, count);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = i; k < n16; k += stride) p[k] = make_uint4(0, 0, 0, 0);
+  if (i < ntail) tail[i] = 0;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  size_t n16 = bytes / 16, ntail = bytes % 16;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint4*)p, n16,
+                     (unsigned char*)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+}  // namespace tacaw
