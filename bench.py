@@ -1,0 +1,337 @@
+#!/usr/bin/env python3
+"""Benchmark of the TACAW hot path on one MI355X.
+
+Workload (one "step"): the 512 x 512 grid class of the batched uneven configuration - 8 rocksalt
+specimens of 160 x 160 Angstrom with 10, 20, ..., 80 slices of 2 Angstrom, a 100 keV probe
+(30 mrad, Cs = 0) scanned over 8 x 8 positions, 256 snapshots at 5 fs.  One step runs the whole
+path from atom positions resident in HBM: slice potentials of every snapshot, batched multislice of
+all 8 x 64 x 256 waves (8 position chunks of 8 positions, every chunk one uneven batched call),
+periodograms accumulated over positions, Kubo correction and normalisation of the 256-bin
+S(q, omega) of every specimen.
+
+Metric: snapshot-slice steps per second = (probe positions x snapshots x sum of slices) / step time.
+Side legs (outside the timed region): the plain one-snapshot-per-launch path on a labelled subset
+(batched vs plain), and the adjoint/forward time ratio on the differentiation configuration.
+
+Prints ONE JSON line.  Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--snapshots", type=int, default=256, help="trajectory length per specimen")
+    p.add_argument("--specimens", type=int, default=8, help="specimens of the 512^2 class (<= 8)")
+    p.add_argument("--pos-chunk", type=int, default=8, help="probe positions per batched call")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-legs", action="store_true", help="skip the plain and adjoint legs")
+    p.add_argument("--cpu-budget-s", type=float, default=20.0)
+    p.add_argument("--profile-slice-step", action="store_true",
+                   help="short run for counter collection: one batched 512^2 multislice call of "
+                        "the workload (8 snapshots) and a 1 GiB device copy as HBM calibration")
+    return p.parse_args()
+
+
+# ------------------------------------------------------------------------------------------------
+def make_specimens(n_spec, T, device):
+    import torch
+    from workloads.configs import c3_specimens, make_workload
+    specs = [c for c in c3_specimens() if c["n"] == (512, 512)][:n_spec]
+    out = []
+    for cfg in specs:
+        w = make_workload(cfg, n_snap=T, generate=False, name=f"c3-512-S{cfg['n_slices']}")
+        from workloads.trajectory import harmonic_trajectory
+        w.positions = harmonic_trajectory(w.extra["structure"], T, cfg["dt"], cfg["seed"],
+                                          device=device)
+        w.species_dev = torch.from_numpy(w.species).to(device)
+        out.append(w)
+    return out
+
+
+def run_step(tw, ctx, ws, Vs, exits, Ps, Ss, pos_chunk, events=None):
+    """One pass of the whole hot path over the batch."""
+    spec_objs = [tw.specimen_from(w) for w in ws]
+    for w, sp, V in zip(ws, spec_objs, Vs):
+        tw.tacaw_build_potentials(ctx, sp, w.positions, w.species_dev, w.ff, V)
+    P = ws[0].n_pos
+    for c0 in range(0, P, pos_chunk):
+        jobs = []
+        for w, sp, V, ex in zip(ws, spec_objs, Vs, exits):
+            b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[c0:c0 + pos_chunk])
+            jobs.append(tw.MsJob(sp, b, V, ex))
+        tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
+        for w, ex, Pacc in zip(ws, exits, Ps):
+            tw.tacaw_periodogram(ctx, ex, w.n_e, w.hop, Pacc, accumulate=c0 > 0)
+    for w, Pacc, S in zip(ws, Ps, Ss):
+        opts = tw.SpectrumOpts(w.dt_fs, w.temperature_k, w.n_e, w.hop, w.nx, w.ny)
+        tw.tacaw_spectrum_finalize(ctx, Pacc, opts, S)
+
+
+def plain_leg(tw, ctx, ws, Vs):
+    """Plain one-snapshot-per-launch path vs batched on the same labelled subset:
+    the 40-slice specimen, 4 probe positions, 32 snapshots."""
+    import torch
+    w = [x for x in ws if x.n_slices == 40][0] if any(x.n_slices == 40 for x in ws) else ws[-1]
+    V = Vs[ws.index(w)][:32].contiguous()
+    ex = torch.empty((32, 4, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+    sp = tw.specimen_from(w)
+    b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[:4])
+    steps = 32 * 4 * w.n_slices
+    out = {}
+    for name, mode in (("plain", tw.MODE_PLAIN), ("batched", tw.MODE_BATCHED)):
+        tw.tacaw_multislice(ctx, [tw.MsJob(sp, b, V, ex)], mode=mode)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tw.tacaw_multislice(ctx, [tw.MsJob(sp, b, V, ex)], mode=mode)
+        torch.cuda.synchronize()
+        out[name] = steps * reps / (time.perf_counter() - t0)
+    return dict(subset=f"{w.name}: 4 positions x 32 snapshots x {w.n_slices} slices, 512^2",
+                plain_slice_steps_per_s=out["plain"], batched_slice_steps_per_s=out["batched"],
+                batched_over_plain=out["batched"] / out["plain"])
+
+
+def adjoint_leg(tw):
+    """Adjoint/forward time ratio on the differentiation configuration (256^2, 20 slices,
+    128 snapshots, B/N-like layers): checkpointed forward vs checkpointed adjoint."""
+    import torch
+    from workloads import make_workload
+    ctx = tw.context(0)
+    w = make_workload("c4", device="cuda:0")
+    sp, bm = tw.specimen_from(w), tw.beam_from(w)
+    T, S = w.n_snap, w.n_slices
+    k = math.ceil(math.sqrt(S))
+    nck = (S + k - 1) // k
+    xyz = w.positions
+    spc = torch.from_numpy(w.species).to("cuda:0")
+    V = torch.empty((T, S, w.ny, w.nx), dtype=torch.float32, device="cuda:0")
+    tw.tacaw_build_potentials(ctx, sp, xyz, spc, w.ff, V)
+    ex = torch.empty((T, 1, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+    ck = torch.empty((T, 1, nck, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+    gex = torch.randn((T, 1, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+    gV = torch.empty_like(V)
+    gxy = torch.empty((T, xyz.shape[1], 2), dtype=torch.float32, device="cuda:0")
+
+    def fwd():
+        tw.tacaw_multislice(ctx, [tw.MsJob(sp, bm, V, ex, ck)], ckpt_stride=k, mode=tw.MODE_BATCHED)
+
+    def adj():
+        tw.tacaw_multislice_adjoint(ctx, [tw.MsJob(sp, bm, V, None, ck)], k, [gex], [gV])
+
+    def adj_xy():
+        adj()
+        tw.tacaw_build_potentials_backward(ctx, sp, xyz, spc, w.ff, gV, gxy)
+
+    def timeit(f, reps=3):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    tf, ta, tax = timeit(fwd), timeit(adj), timeit(adj_xy)
+    return dict(config="B/N-like 16x9x10 cells, 256^2, 20 slices, 128 snapshots, ckpt stride 5",
+                forward_ms=tf * 1e3, adjoint_ms=ta * 1e3, adjoint_plus_positions_ms=tax * 1e3,
+                adjoint_over_forward=ta / tf, adjoint_with_positions_over_forward=tax / tf)
+
+
+# ------------------------------------------------------------------------------------------------
+def cpu_baseline(budget_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: one 512^2
+    specimen slab of 10 slices, 2 snapshots x 2 probe positions (40 slice steps, 20 potential
+    maps), timed on the host cores; scaled to the workload's mix of one potential map per 64
+    probe positions."""
+    from threadpoolctl import threadpool_info
+    from oracle import multislice as o_ms
+    from oracle import potential as o_pot
+    from workloads.configs import c3_specimens, make_workload
+    cfg = [c for c in c3_specimens() if c["n"] == (512, 512)][0]
+    w = make_workload(cfg, n_snap=2, name="cpu-sample")
+    w.probe_xy = w.probe_xy[:2]
+    t0 = time.perf_counter()
+    V, _ = o_pot.potentials(w.positions, w.species, w.ff, w)
+    t_pot = time.perf_counter() - t0
+    n_maps = V.shape[0] * V.shape[1]
+    t0 = time.perf_counter()
+    ex = o_ms.exit_waves(V, w, w)
+    t_ms = time.perf_counter() - t0
+    n_steps = V.shape[0] * w.probe_xy.shape[0] * w.n_slices
+    per_step = t_ms / n_steps + (t_pot / n_maps) / 64.0
+    threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
+    return {"value": 1.0 / per_step, "unit": "snapshot-slice steps/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"512^2 rocksalt slab, 10 slices, 2 snapshots x 2 probe positions: {n_maps} "
+                      f"potential maps in {t_pot:.1f} s, {n_steps} dense-DFT slice steps in "
+                      f"{t_ms:.1f} s; scaled to 1 map per 64 positions",
+            "wall_s": t_pot + t_ms}
+
+
+def traffic_record():
+    """HBM traffic of the dominant kernel from the committed counter summary, if it was taken on
+    the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_slice_step_512.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2401_15599_amd", "csrc", "ms_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha256_16") != h:
+        return None
+    return rec
+
+
+# ------------------------------------------------------------------------------------------------
+def profile_slice_step(args):
+    """Counter-collection run: the calibration copy, then two batched multislice calls of the
+    benchmark workload at 8 snapshots (512 waves of 512^2, 2 GiB per pass, well above the 256 MB
+    last-level cache), with the per-launch algorithmic bytes printed for comparison."""
+    import torch
+    import paper_2401_15599_amd as tw
+    ctx = tw.context(0)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)   # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    T = 8
+    ws = make_specimens(args.specimens, T, "cuda:0")
+    Vs = [torch.empty((T, w.n_slices, w.ny, w.nx), dtype=torch.float32, device="cuda:0") for w in ws]
+    exits = [torch.empty((T, args.pos_chunk, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+             for w in ws]
+    for w, V in zip(ws, Vs):
+        tw.tacaw_build_potentials(ctx, tw.specimen_from(w), w.positions, w.species_dev, w.ff, V)
+    jobs = []
+    for w, V, ex in zip(ws, Vs, exits):
+        b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[:args.pos_chunk])
+        jobs.append(tw.MsJob(tw.specimen_from(w), b, V, ex))
+    tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
+    torch.cuda.synchronize()
+    tw.tacaw_set_timing(ctx, True)
+    tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
+    torch.cuda.synchronize()
+    out = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col")}
+    tw.tacaw_set_timing(ctx, False)
+    for k, v in out.items():
+        v["algo_bytes_per_launch"] = v["algo_bytes"] / max(1, v["launches"])
+        v["avg_ms"] = v["total_ms"] / max(1, v["launches"])
+        v["algo_GBps"] = v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9
+    print(json.dumps({"calibration_copy_bytes": 2 * (1 << 30), "slice_step": out}))
+
+
+def main():
+    args = parse()
+    if args.profile_slice_step:
+        profile_slice_step(args)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+    import torch
+    import paper_2401_15599_amd as tw
+
+    ctx = tw.context(0)
+    tune = os.path.join(ROOT, "profiles", "tuning_gfx950.jsonl")
+    if os.path.exists(tune):
+        tw.tacaw_load_tuning(ctx, tune)
+    log(f"[bench] generating {args.specimens} specimens x {args.snapshots} snapshots on the GPU")
+    ws = make_specimens(args.specimens, args.snapshots, "cuda:0")
+    T = args.snapshots
+    for w in ws:
+        w.n_e = min(256, T)
+        w.hop = w.n_e
+    Vs = [torch.empty((T, w.n_slices, w.ny, w.nx), dtype=torch.float32, device="cuda:0") for w in ws]
+    exits = [torch.empty((T, args.pos_chunk, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+             for w in ws]
+    Ps = [torch.empty((w.n_e, w.ny, w.nx), dtype=torch.float32, device="cuda:0") for w in ws]
+    Ss = [torch.empty((w.n_e, w.ny, w.nx), dtype=torch.float32, device="cuda:0") for w in ws]
+    slice_steps = sum(w.n_pos * T * w.n_slices for w in ws)
+    log(f"[bench] {slice_steps / 1e6:.2f} M snapshot-slice steps per step; "
+        f"HBM in use {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+    for i in range(args.warmup):
+        run_step(tw, ctx, ws, Vs, exits, Ps, Ss, args.pos_chunk)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    tw.tacaw_set_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run_step(tw, ctx, ws, Vs, exits, Ps, Ss, args.pos_chunk)
+        torch.cuda.synchronize()
+        log(f"[bench] step {i + 1}/{args.steps} done")
+    dt = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    kinds = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col", "sf", "pot_ifft", "pgram")}
+    tw.tacaw_set_timing(ctx, False)
+    ms_step = dt / args.steps * 1e3
+    value = slice_steps * args.steps / dt
+    # dominant kernel among the slice-step passes
+    dom = max(("row", "col"), key=lambda k: kinds[k]["total_ms"])
+    kd = kinds[dom]
+    achieved = kd["algo_bytes"] / (kd["total_ms"] * 1e-3) / 1e9 if kd["total_ms"] > 0 else 0.0
+    rec = traffic_record()
+    roofline = {"bound": "hbm", "kernel": f"slice step, {dom} pass (512^2)",
+                "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS,
+                "traffic": (rec or {}).get(f"{dom}_bytes_per_launch_scaled") if rec else None,
+                "algo_bytes_per_launch": kd["algo_bytes"] / max(1, kd["launches"]),
+                "avg_launch_ms": kd["total_ms"] / max(1, kd["launches"])}
+    breakdown = {k: {"launches": v["launches"], "ms": v["total_ms"] / args.steps,
+                     "algo_GBps": (v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] else None}
+                 for k, v in kinds.items()}
+    ms_time = kinds["row"]["total_ms"] + kinds["col"]["total_ms"]
+    extra = {"multislice_only_slice_steps_per_s": slice_steps * args.steps / (ms_time * 1e-3)
+             if ms_time else None,
+             "kernel_ms_per_step": breakdown}
+    if not args.no_legs:
+        log("[bench] plain vs batched leg")
+        extra["plain_vs_batched"] = plain_leg(tw, ctx, ws, Vs)
+        log("[bench] adjoint/forward leg")
+        del exits, Ss
+        torch.cuda.empty_cache()
+        extra["adjoint"] = adjoint_leg(tw)
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline (host cores)")
+        cpu = cpu_baseline(args.cpu_budget_s)
+    line = {
+        "metric": "snapshot-slice steps/sec at 512^2 (batched vs plain) + adjoint/forward time ratio",
+        "value": value, "unit": "snapshot-slice steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64/f32", "data": "synthetic (seeded harmonic trajectories)",
+        "config": {"workload": "batched-uneven 512^2 class: 8 rocksalt specimens 160x160 A, "
+                               "10..80 slices, 100 keV 30 mrad probe at 8x8 positions, "
+                               f"{T} snapshots at 5 fs, S(q,w) with {min(256, T)} bins",
+                   "grid": 512, "specimens": len(ws), "probe_positions": ws[0].n_pos,
+                   "snapshots": T, "slice_steps_per_step": slice_steps, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -255,6 +255,25 @@ int tacaw_load_tuning(tacaw_ctx* ctx, const char* cache_path);
 /* Current schedule for grid n as text ("row=<plan> col=<plan> C=<cols>"), for logging. */
 const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n);
 
+/* ----------------------------------------------------------------------------------------------
+ * Kernel timing instrumentation (for benchmarks and roofline reports).
+ * With timing enabled, every slice-step launch (kinds "row", "col", "row_adj", "col_adj"), every
+ * structure-factor launch ("sf"), potential inverse FFT ("pot_ifft") and periodogram ("pgram") is
+ * bracketed by HIP events recorded on the stream it runs on, and its algorithmic HBM bytes are
+ * recorded: x pass 8 (wave in) + 8 (wave out) [+ 8 checkpoint] [+ 8 stash] per image element and
+ * wave, plus 4 per element of each V row read once for all probe positions (8 with dL/dV); y pass
+ * 16 per element and wave.  Batched multislice calls then launch eagerly instead of replaying
+ * their hipGraph (the same kernels and grids).
+ * tacaw_get_timing waits for the recorded events, sums launches, milliseconds and bytes of one kind
+ * (all kinds for NULL or ""), and forgets them. */
+typedef struct {
+  int64_t launches;
+  double total_ms;
+  double algo_bytes;
+} tacaw_kernel_stats;
+int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable);
+int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,12 +11,16 @@ from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
 import numpy as np
+# torch carries its own HIP runtime (soname libamdhip64.so.7).  Loading it before the library makes
+# libtacaw bind to that same runtime; the other order puts two HIP runtimes in the process and
+# torch then finds no GPU.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtacaw.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_15599_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2401_15599_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -46,6 +50,11 @@ class _Job(ctypes.Structure):
     _fields_ = [("spec", ctypes.POINTER(_Spec)), ("beam", ctypes.POINTER(_Beam)),
                 ("n_snap", ctypes.c_int32), ("V", ctypes.c_void_p), ("exit", ctypes.c_void_p),
                 ("ckpt", ctypes.c_void_p)]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("algo_bytes", ctypes.c_double)]
 
 
 class _Opts(ctypes.Structure):
@@ -81,6 +90,8 @@ _SIGS = {
     "tacaw_autotune": ([_P, _I, _I, ctypes.c_char_p, _P], ctypes.c_int),
     "tacaw_load_tuning": ([_P, ctypes.c_char_p], ctypes.c_int),
     "tacaw_describe_schedule": ([_P, _I], ctypes.c_char_p),
+    "tacaw_set_timing": ([_P, _I], ctypes.c_int),
+    "tacaw_get_timing": ([_P, ctypes.c_char_p, ctypes.POINTER(KernelStats)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -333,3 +344,13 @@ def tacaw_load_tuning(ctx, cache_path):
 
 def tacaw_describe_schedule(ctx, n):
     return _lib.tacaw_describe_schedule(ctx.handle, n).decode()
+
+
+def tacaw_set_timing(ctx, enable):
+    _check(_lib.tacaw_set_timing(ctx.handle, 1 if enable else 0))
+
+
+def tacaw_get_timing(ctx, kind=None):
+    st = KernelStats()
+    _check(_lib.tacaw_get_timing(ctx.handle, kind.encode() if kind else None, ctypes.byref(st)))
+    return dict(launches=st.launches, total_ms=st.total_ms, algo_bytes=st.algo_bytes)

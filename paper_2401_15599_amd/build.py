@@ -1,6 +1,6 @@
 """Build the gfx950 library libtacaw.so in-tree with hipcc (no JIT, no torch extension machinery).
 
-    python -m paper_2401_15599_amd.build          # or build() from Python
+    python paper_2401_15599_amd/build.py          # or __graft_entry__.build()
 
 Every translation unit is compiled in parallel, then linked into a shared library next to this
 file.  Device code is built with packed-FP32 instructions disabled.  Also builds the CPU emulation

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -173,6 +174,8 @@ struct Cached {
 
 struct Sched {
   int row_plan = 0, col_plan = 0, C = 0;
+  int col_kind = 1;    // 0 staged tile, 1 block kernel
+  int pp = 1;          // block kernel: ping-pong LDS exchange regions
 };
 
 }  // namespace
@@ -188,11 +191,22 @@ struct tacaw_ctx {
   std::map<int, Sched> sched;
   hipStream_t cap_stream = nullptr;
   std::string desc;
+  // opt-in timing instrumentation
+  struct Timed {
+    std::string kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool timing = false;
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> ev_pool;
 
   ~tacaw_ctx() {
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& t : timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto& c : cache) {
       if (c.second.dev) (void)hipFree(c.second.dev);
       if (c.second.host) (void)hipHostFree(c.second.host);
@@ -226,6 +240,32 @@ void* workspace(tacaw_ctx* c, const std::string& name, size_t bytes) {
   }
   b.bytes = sz;
   return b.p;
+}
+
+hipEvent_t pool_event(tacaw_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hip_check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+// run `launch`; with timing enabled, bracket it with events on its stream and record the
+// launch's algorithmic bytes under `kind`
+template <class F> void timed_launch(tacaw_ctx* c, hipStream_t st, const char* kind, double bytes,
+                                     F&& launch) {
+  if (!c->timing) {
+    launch();
+    return;
+  }
+  hipEvent_t a = pool_event(c), b = pool_event(c);
+  hip_check(hipEventRecord(a, st), "hipEventRecord");
+  launch();
+  hip_check(hipEventRecord(b, st), "hipEventRecord");
+  c->timed.push_back({kind, a, b, bytes});
 }
 
 // content-addressed copy of a small host table in device memory (pinned staging kept alive)
@@ -287,22 +327,24 @@ Sched schedule_for(tacaw_ctx* c, int n) {
   Sched s;
   s.row_plan = 0;
   s.col_plan = 0;
-  switch (n) {
-    case 16: s.C = 16; break;
-    case 32: s.C = 32; break;
-    case 64: s.C = 64; break;
-    case 128: s.C = 64; break;
-    case 256: s.C = 32; break;
-    case 512: s.C = 16; break;
-    default: s.C = 8; break;
-  }
+  s.col_kind = 1;
+  s.pp = 1;
+  s.C = 16;   // 128-byte row segments
   return s;
 }
 
-int clamp_cols(tacaw_ctx* c, int ny, int plan, int C, int nx) {
-  C = std::min(C, nx);
-  while (C > 1 && col_lds_bytes(ny, plan, C) > c->max_lds) C /= 2;
-  return C;
+// fit the column tile to the image width, the workgroup size and the LDS budget
+Sched fit_cols(tacaw_ctx* c, int ny, Sched s, int nx) {
+  s.C = std::min(s.C, nx);
+  if (s.col_kind == 1) {
+    const int L = plan_lanes(ny, s.col_plan);
+    while (s.C > 1 && s.C * L > 1024) s.C /= 2;
+    if (s.pp && col_block_lds_bytes(ny, s.col_plan, s.C, 1) > c->max_lds) s.pp = 0;
+    while (s.C > 1 && col_block_lds_bytes(ny, s.col_plan, s.C, s.pp) > c->max_lds) s.C /= 2;
+  } else {
+    while (s.C > 1 && col_lds_bytes(ny, s.col_plan, s.C) > c->max_lds) s.C /= 2;
+  }
+  return s;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -312,6 +354,7 @@ struct ClassPlan {
   std::vector<int2> groups;        // (job, t) sorted by S descending
   std::vector<int4> waves;         // (job, t, p, S) same order
   std::vector<int> group_S, wave_S;
+  std::vector<long> group_wave_prefix;   // waves in groups [0, g)
   std::vector<int4> plane_waves, probe_waves;
   int Smax = 0;
 };
@@ -405,9 +448,11 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
     std::stable_sort(cp.groups.begin(), cp.groups.end(), [&](int2 a, int2 x) {
       return b.jobs[a.x].S > b.jobs[x.x].S;
     });
+    cp.group_wave_prefix.push_back(0);
     for (auto g : cp.groups) {
       const MsJobDev& d = b.jobs[g.x];
       cp.group_S.push_back(d.S);
+      cp.group_wave_prefix.push_back(cp.group_wave_prefix.back() + d.P);
       for (int p = 0; p < d.P; ++p) {
         int4 w = make_int4(g.x, g.y, p, d.S);
         cp.waves.push_back(w);
@@ -424,19 +469,35 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
 struct Launcher {
   tacaw_ctx* c;
   hipStream_t st;
-  void row(int n, const Sched& sc, bool adj, RowArgs a) {
+  // waves: number of waves the launch covers (for the byte model only)
+  void row(int n, const Sched& sc, bool adj, RowArgs a, long waves) {
     if (a.n_groups <= 0) return;
     const int lines = row_lines_per_wave(n, sc.row_plan);
     const long tasks = (long)a.n_groups * a.ny;
     long g = (tasks + (long)kWaves * lines - 1) / ((long)kWaves * lines);
     g = std::min<long>(g, (long)c->n_cu * 8);
-    hip_check(launch_row(n, sc.row_plan, adj, a, (int)std::max<long>(g, 1), st), "row kernel");
+    // bytes per image element: wave in 8, out 8, checkpoint 8, stash 8; per V row 4 (+4 for dL/dV)
+    const double img = (double)n * a.ny;
+    double per_wave = 8.0 + (a.write_out ? 8.0 : 0.0) + (a.store_ckpt ? 8.0 : 0.0) +
+                      (a.stash_slot >= 0 ? 8.0 : 0.0);
+    double bytes = img * (per_wave * waves + (adj ? 8.0 : 4.0) * a.n_groups);
+    timed_launch(c, st, adj ? "row_adj" : "row", bytes, [&] {
+      hip_check(launch_row(n, sc.row_plan, adj, a, (int)std::max<long>(g, 1), st), "row kernel");
+    });
   }
   void col(int ny, const Sched& sc, bool f, bool i, ColArgs a) {
     if (a.n_waves <= 0) return;
+    a.C = sc.C;
+    a.pingpong = sc.pp;
     const long tasks = (long)a.n_waves * (a.nx / a.C);
-    long g = std::min<long>(tasks, (long)c->n_cu * 8);
-    hip_check(launch_col(ny, sc.col_plan, f, i, a, (int)std::max<long>(g, 1), st), "column kernel");
+    // block kernel: one or two resident workgroups per CU (LDS bound); staged: up to 8
+    const long per_cu = sc.col_kind == 1 ? std::max(1, c->max_lds / std::max(1, col_block_lds_bytes(ny, sc.col_plan, sc.C, sc.pp))) : 8;
+    long g = std::min<long>(tasks, (long)c->n_cu * per_cu);
+    const double bytes = 16.0 * (double)a.nx * ny * a.n_waves;
+    timed_launch(c, st, a.conj_prop ? "col_adj" : "col", bytes, [&] {
+      hip_check(launch_col(ny, sc.col_plan, sc.col_kind, f, i, a, (int)std::max<long>(g, 1), st),
+                "column kernel");
+    });
   }
 };
 
@@ -444,8 +505,8 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
   Launcher L{c, st};
   for (const ClassPlan& cp : b.classes) {
     const Sched rs = schedule_for(c, cp.nx);
-    Sched cs = schedule_for(c, cp.ny);
-    cs.C = clamp_cols(c, cp.ny, cs.col_plan, cs.C, cp.nx);
+    const Sched cs = fit_cols(c, cp.ny, schedule_for(c, cp.ny), cp.nx);
+    // the staged init kernels use the same column count (their LDS tile is the smaller one)
     auto do_range = [&](const int2* groups, int ng, const int4* waves, const std::vector<int>& gS,
                         const std::vector<int>& wS, const int4* plane, int nplane,
                         const int4* probe, int nprobe) {
@@ -479,7 +540,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ra.stash_slot = -1;
         ra.write_out = 1;
         ra.ny = cp.ny;
-        L.row(cp.nx, rs, false, ra);
+        L.row(cp.nx, rs, false, ra, active_prefix(wS, s));
         const int n_mid = active_prefix(wS, s + 1), n_all = active_prefix(wS, s);
         ColArgs ca{};
         ca.jobs = b.jobs_dev;
@@ -534,7 +595,8 @@ std::string graph_key(const MsBuild& b, int ckpt_stride, int mode, tacaw_ctx* c)
   for (auto& cp : b.classes) {
     Sched a = schedule_for(c, cp.nx), s2 = schedule_for(c, cp.ny);
     k += "|" + std::to_string(cp.nx) + "," + std::to_string(a.row_plan) + "," +
-         std::to_string(s2.col_plan) + "," + std::to_string(s2.C);
+         std::to_string(s2.col_plan) + "," + std::to_string(s2.C) + "," +
+         std::to_string(s2.col_kind) + "," + std::to_string(s2.pp);
     k.append((const char*)cp.groups.data(), cp.groups.size() * sizeof(int2));
   }
   return k;
@@ -671,9 +733,13 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
       a.pref = (float)(2.0 * kPi * kA0 * kE4pe0 / (spec->lx * spec->ly));
       a.nmax = nmax;
       a.n_maps = nt * S;
-      hip_check(launch_structure_factor(a, st), "structure-factor kernel");
-      hip_check(launch_ifft2_real(spec->nx, spec->ny, vk, V + (size_t)t0 * S * img, nt * S, st),
-                "potential inverse FFT");
+      timed_launch(ctx, st, "sf", 8.0 * img * nt * S, [&] {
+        hip_check(launch_structure_factor(a, st), "structure-factor kernel");
+      });
+      timed_launch(ctx, st, "pot_ifft", 36.0 * img * nt * S, [&] {
+        hip_check(launch_ifft2_real(spec->nx, spec->ny, vk, V + (size_t)t0 * S * img, nt * S, st),
+                  "potential inverse FFT");
+      });
     }
   });
 }
@@ -742,8 +808,8 @@ int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, i
     hipStream_t st = (hipStream_t)stream;
     MsBuild b = build_ms(ctx, n_jobs, jobs, ckpt_stride, st, false, nullptr, nullptr);
     b.jobs_dev = upload_vec(ctx, b.jobs, st, "jobs");
-    if (mode == TACAW_MODE_PLAIN) {
-      run_forward(ctx, b, ckpt_stride, mode, st);
+    if (mode == TACAW_MODE_PLAIN || ctx->timing) {
+      run_forward(ctx, b, ckpt_stride, mode, st);   // timing: eager launches bracketed by events
       return;
     }
     const std::string key = graph_key(b, ckpt_stride, mode, ctx);
@@ -808,8 +874,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
     Launcher L{ctx, st};
     for (const ClassPlan& cp : b.classes) {
       const Sched rs = schedule_for(ctx, cp.nx);
-      Sched cs = schedule_for(ctx, cp.ny);
-      cs.C = clamp_cols(ctx, cp.ny, cs.col_plan, cs.C, cp.nx);
+      const Sched cs = fit_cols(ctx, cp.ny, schedule_for(ctx, cp.ny), cp.nx);
       // process jobs of equal slice count together: segments then align
       std::map<int, std::pair<std::vector<int2>, std::vector<int4>>, std::greater<int>> byS;
       for (auto g : cp.groups) byS[b.jobs[g.x].S].first.push_back(g);
@@ -849,7 +914,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
             ra.stash_slot = s - s0;
             ra.write_out = (s < s1 - 1) ? 1 : 0;
             ra.ny = cp.ny;
-            L.row(cp.nx, rs, false, ra);
+            L.row(cp.nx, rs, false, ra, nw);
             if (s < s1 - 1) {
               ColArgs fa = ca;
               fa.s = s;
@@ -872,7 +937,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
             ra.stash_slot = s - s0;
             ra.write_out = s > 0 ? 1 : 0;
             ra.ny = cp.ny;
-            L.row(cp.nx, rs, true, ra);
+            L.row(cp.nx, rs, true, ra, nw);
             if (s > 0) {
               ColArgs aa = ca;
               aa.s = s - 1;
@@ -916,7 +981,11 @@ int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, in
     a.hop = hop;
     a.G = (n_snap - n_e) / hop + 1;
     a.accumulate = accumulate ? 1 : 0;
-    hip_check(launch_periodogram(a, (hipStream_t)stream), "periodogram kernel");
+    const double bytes = 8.0 * nx * ny * (double)n_e * a.G * n_pos +
+                         (accumulate ? 8.0 : 4.0) * nx * ny * (double)n_e;
+    timed_launch(ctx, (hipStream_t)stream, "pgram", bytes, [&] {
+      hip_check(launch_periodogram(a, (hipStream_t)stream), "periodogram kernel");
+    });
   });
 }
 
@@ -1007,10 +1076,44 @@ int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int
 }
 
 // ------------------------------------------------------------------------------------------------
+// timing instrumentation
+int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable) {
+  return guarded([&] {
+    use_device(ctx);
+    ctx->timing = enable != 0;
+  });
+}
+
+int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out) {
+  return guarded([&] {
+    use_device(ctx);
+    if (!out) fail(TACAW_E_ARG, "null output");
+    *out = tacaw_kernel_stats{0, 0.0, 0.0};
+    std::vector<tacaw_ctx::Timed> keep;
+    for (auto& t : ctx->timed) {
+      if (kind && *kind && t.kind != kind) {
+        keep.push_back(t);
+        continue;
+      }
+      hip_check(hipEventSynchronize(t.b), "hipEventSynchronize");
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, t.a, t.b), "hipEventElapsedTime");
+      out->launches += 1;
+      out->total_ms += ms;
+      out->algo_bytes += t.bytes;
+      ctx->ev_pool.push_back(t.a);
+      ctx->ev_pool.push_back(t.b);
+    }
+    ctx->timed.swap(keep);
+  });
+}
+
+// ------------------------------------------------------------------------------------------------
 // autotuning
 static std::string sched_line(int n, const Sched& s) {
   std::ostringstream o;
-  o << "row=" << plan_name(n, s.row_plan) << " col=" << plan_name(n, s.col_plan) << " C=" << s.C;
+  o << "row=" << plan_name(n, s.row_plan) << " col=" << plan_name(n, s.col_plan) << " C=" << s.C
+    << (s.col_kind == 1 ? " block" : " staged") << (s.pp ? " pingpong" : "");
   return o.str();
 }
 
@@ -1040,6 +1143,8 @@ int tacaw_load_tuning(tacaw_ctx* ctx, const char* path) {
       s.row_plan = num("row");
       s.col_plan = num("col");
       s.C = num("C");
+      s.col_kind = num("kind");
+      s.pp = num("pp");
       if (!pow2_in(n, 16, 1024) || s.row_plan < 0 || s.row_plan >= n_plans(n) || s.col_plan < 0 ||
           s.col_plan >= n_plans(n) || s.C < 1)
         fail(TACAW_E_ARG, "malformed tuning entry");
@@ -1100,16 +1205,25 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
         ra.stash_slot = -1;
         ra.write_out = 1;
         ra.ny = n;
-        L.row(n, sc, false, ra);
+        L.row(n, sc, false, ra, (long)cp.waves.size());
       });
+      if (std::getenv("TACAW_TUNE_VERBOSE"))
+        std::fprintf(stderr, "[tune] n=%d row plan %s: %.3f ms\n", n, plan_name(n, rp), ms / 5);
       if (ms < best_row) { best_row = ms; best.row_plan = rp; }
     }
     for (int cpn = 0; cpn < n_plans(n); ++cpn)
+      for (int kind = 0; kind < 2; ++kind)
+      for (int pp = 0; pp < (kind == 1 ? 2 : 1); ++pp)
       for (int C = 8; C <= 64; C *= 2) {
-        if (C > n || col_lds_bytes(n, cpn, C) > ctx->max_lds) continue;
+        if (C > n) continue;
+        if (kind == 0 && col_lds_bytes(n, cpn, C) > ctx->max_lds) continue;
+        if (kind == 1 && (C * plan_lanes(n, cpn) > 1024 ||
+                          col_block_lds_bytes(n, cpn, C, pp) > ctx->max_lds)) continue;
         Sched sc = best;
         sc.col_plan = cpn;
         sc.C = C;
+        sc.col_kind = kind;
+        sc.pp = pp;
         float ms = time_it([&] {
           ColArgs ca{};
           ca.jobs = b.jobs_dev;
@@ -1123,7 +1237,16 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
           ca.scale = 1.0f / (float)img;
           L.col(n, sc, true, true, ca);
         });
-        if (ms < best_col) { best_col = ms; best.col_plan = cpn; best.C = C; }
+        if (std::getenv("TACAW_TUNE_VERBOSE"))
+          std::fprintf(stderr, "[tune] n=%d col plan %s kind=%d pp=%d C=%d: %.3f ms\n", n,
+                       plan_name(n, cpn), kind, pp, C, ms / 5);
+        if (ms < best_col) {
+          best_col = ms;
+          best.col_plan = cpn;
+          best.C = C;
+          best.col_kind = kind;
+          best.pp = pp;
+        }
       }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1145,6 +1268,8 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
           s.row_plan = num("row");
           s.col_plan = num("col");
           s.C = num("C");
+          s.col_kind = num("kind");
+          s.pp = num("pp");
           all[num("n")] = s;
         }
       }
@@ -1152,7 +1277,8 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
       std::ofstream o(cache_path);
       for (auto& kv : all)
         o << "{\"arch\": \"gfx950\", \"n\": " << kv.first << ", \"row\": " << kv.second.row_plan
-          << ", \"col\": " << kv.second.col_plan << ", \"C\": " << kv.second.C << "}\n";
+          << ", \"col\": " << kv.second.col_plan << ", \"C\": " << kv.second.C
+          << ", \"kind\": " << kv.second.col_kind << ", \"pp\": " << kv.second.pp << "}\n";
     }
   });
 }

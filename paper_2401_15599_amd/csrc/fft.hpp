@@ -164,8 +164,9 @@ template <int N_, int L_, int... Rs> struct Plan {
     return total;
   }
   static constexpr int NTW = twiddle_count() > 0 ? twiddle_count() : 1;
-  // LDS words (float2) needed per line for the exchanges, with padding p + p/8
-  static constexpr int LDS_LINE = N_ + N_ / 8 + 2;
+  // LDS words (float2) per line: room for the exchange padding p + p/8, rounded up to 1 mod 16
+  // so that 16 adjacent lines staged side by side (column tiles) fall in 16 distinct bank pairs
+  static constexpr int LDS_LINE = ((N_ + N_ / 8 + 2 + 14) / 16) * 16 + 1;
 };
 
 TACAW_HD int lds_pad(int p) { return p + (p >> 3); }
@@ -255,12 +256,43 @@ __device__ __forceinline__ void fft_rec(float2* v, const float2* tw, float2* lds
   }
 }
 
+// Workgroup variant: the L lanes of a line may sit in different wavefronts, so every exchange is a
+// workgroup barrier.  Exchanges alternate between two LDS regions (running parity `buf`); a region
+// is rewritten only two exchanges after it was read, with a barrier in between, so one barrier per
+// exchange suffices.  With lds1 == lds0 (single buffer) a second barrier guards the rewrite.
+template <int N, int L, bool INV, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_block_rec(float2* v, const float2* tw, float2* lds0,
+                                              float2* lds1, int l, int& buf) {
+  constexpr int E = N / L, B = E / R;
+  stage_compute<N, L, R, NS, INV>(v, tw);
+  if constexpr (sizeof...(Rest) > 0) {
+    float2* lds = buf ? lds1 : lds0;
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_pad(stage_out_pos<N, L, R, NS>(l, i, r))] = v[i + B * r];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
+    if (lds0 == lds1) __syncthreads();
+    buf ^= 1;
+    fft_block_rec<N, L, INV, NS * R, Rest...>(v, (NS > 1) ? tw + B * (R - 1) : tw, lds0, lds1, l,
+                                              buf);
+  }
+}
+
 template <class P> struct FFT;
 template <int N, int L, int... Rs> struct FFT<Plan<N, L, Rs...>> {
   // unnormalised transform of one line held striped in v; lds = this line's exchange region
   template <bool INV>
   __device__ __forceinline__ static void run(float2* v, const float2* tw, float2* lds, int l) {
     fft_rec<N, L, INV, 1, Rs...>(v, tw, lds, l);
+  }
+  // same transform when the line's lanes span several wavefronts of the workgroup
+  template <bool INV>
+  __device__ __forceinline__ static void run_block(float2* v, const float2* tw, float2* lds0,
+                                                   float2* lds1, int l, int& buf) {
+    fft_block_rec<N, L, INV, 1, Rs...>(v, tw, lds0, lds1, l, buf);
   }
 };
 #endif

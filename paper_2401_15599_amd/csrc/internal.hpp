@@ -62,6 +62,7 @@ struct ColArgs {
   int C;                   // columns per tile
   float scale;             // 1/(nx ny), 1/sqrt(nx ny), ...
   int nx;                  // columns per image (all jobs of a launch share nx, ny)
+  int pingpong;            // block kernel: two LDS exchange regions (one barrier per exchange)
 };
 
 // plain batched 2-D transforms of contiguous images (potential build, position gradient)
@@ -75,8 +76,12 @@ struct PlainArgs {
 int n_plans(int n);
 const char* plan_name(int n, int idx);
 hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hipStream_t st);
-hipError_t launch_col(int n, int plan, bool dofwd, bool doinv, const ColArgs& a, int grid,
+// kind 0: LDS-staged tile, whole columns per wavefront; kind 1: block kernel, lanes of a column
+// spread over the workgroup (C * L threads), tile loaded straight into registers
+hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const ColArgs& a, int grid,
                       hipStream_t st);
+int col_block_lds_bytes(int n, int plan, int C, int pingpong);
+int plan_lanes(int n, int plan);
 hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStream_t st);
 hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st);
 int row_lines_per_wave(int n, int plan);

@@ -205,6 +205,82 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
   }
 }
 
+// y pass, block variant: a workgroup of C * L threads owns C adjacent columns; thread (c, l) holds
+// rows l + L j of column c (striped for the column transform), loaded and stored with C-wide row
+// segments.  The next tile is prefetched into registers while the current one is transformed.
+// Twiddles live in a small LDS table (lanes sharing l read the same entry); the per-row propagator
+// factors py stay in registers across tiles of the same job.
+template <class P, bool DOFWD, bool DOINV>
+__global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, CS = P::LDS_LINE, NTW = P::NTW;
+  extern __shared__ float2 lds_mem[];
+  const int C = a.C, nx = a.nx;
+  const int c = (int)threadIdx.x % C, l = (int)threadIdx.x / C;
+  float2* reg0 = lds_mem + c * CS;
+  float2* reg1 = a.pingpong ? lds_mem + (C + c) * CS : reg0;
+  float2* twl = lds_mem + (a.pingpong ? 2 : 1) * C * CS;
+  float2* pyl = twl + L * NTW;                       // [N] propagator factors of the current job
+  if (c == 0) {
+    float2 t[NTW];
+    PlanOps<P>::twiddles(t, l);
+#pragma unroll
+    for (int k = 0; k < NTW; ++k) twl[l * NTW + k] = t[k];
+  }
+  const float2* tw = twl + l * NTW;
+  int buf = 0;
+  const int tpi = nx / C, s = a.s;
+  const long n_tasks = (long)a.n_waves * tpi;
+  float2 nxt[E];
+  float2 nxt_px = make_float2(0.f, 0.f);
+  int nxt_nm = -1;
+  // uniform image base + per-lane 32-bit element offsets
+  auto load = [&](long tk) {
+    const int4 wv = a.waves[tk / tpi];
+    const MsJobDev& J = a.jobs[wv.x];
+    const float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s);
+    const int m = (int)(tk % tpi) * C + c;
+#pragma unroll
+    for (int j = 0; j < E; ++j) nxt[j] = in[(l + L * j) * nx + m];
+    nxt_px = J.px[s * nx + m];
+    nxt_nm = J.nmax[m];
+  };
+  int py_job = -1;
+  long task = blockIdx.x;
+  if (task < n_tasks) load(task);
+  for (; task < n_tasks; task += gridDim.x) {
+    float2 v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = nxt[j];
+    const float2 pxm = nxt_px;
+    const int nm = nxt_nm;
+    const int4 wv = a.waves[task / tpi];
+    const int m = (int)(task % tpi) * C + c;
+    if (wv.x != py_job) {                            // uniform branch
+      __syncthreads();                               // previous tile's readers are done
+      const float2* pys = a.jobs[wv.x].py + s * N;
+      for (int i = threadIdx.x; i < N; i += blockDim.x) pyl[i] = pys[i];
+      __syncthreads();
+      py_job = wv.x;
+    }
+    if (task + gridDim.x < n_tasks) load(task + gridDim.x);
+    if constexpr (DOFWD) FFT<P>::template run_block<false>(v, tw, reg0, reg1, l, buf);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int n = l + L * j;
+      const int ns = n < N / 2 ? n : n - N;
+      float2 d = make_float2(0.f, 0.f);
+      if ((ns < 0 ? -ns : ns) <= nm) d = cmul(pxm, pyl[n]);
+      if (a.conj_prop) d.y = -d.y;
+      v[j] = cscale(cmul(v[j], d), a.scale);
+    }
+    if constexpr (DOINV) FFT<P>::template run_block<true>(v, tw, reg0, reg1, l, buf);
+    const MsJobDev& J = a.jobs[wv.x];
+    float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s);
+#pragma unroll
+    for (int j = 0; j < E; ++j) out[(l + L * j) * nx + m] = v[j];
+  }
+}
+
 // probe: psi_0 in the (kx, y) representation, W = G_y[a(k)] / (sqrt(nx ny) sqrt(n_aperture))
 template <class P>
 __global__ __launch_bounds__(kThreads) void k_probe_init(ColArgs a) {
@@ -397,15 +473,49 @@ void prepare_dynamic_lds(int max_bytes) {
         (void)hipFuncSetAttribute((const void*)k_col<P, true, false>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col<P, false, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_probe_init<P>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colb<P, true, true>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colb<P, true, false>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colb<P, false, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, false>, (hipFuncAttribute)attr, max_bytes);
       });
   (void)hipGetLastError();
 }
 
-hipError_t launch_col(int n, int plan, bool dofwd, bool doinv, const ColArgs& a, int grid,
-                      hipStream_t st) {
+int plan_lanes(int n, int plan) {
+  int L = 0;
+  with_plan(n, plan, [&](auto p) { L = decltype(p)::L; });
+  return L;
+}
+
+int col_block_lds_bytes(int n, int plan, int C, int pingpong) {
+  int tw = 0;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    tw = (P::L * P::NTW + P::N) * (int)sizeof(float2);
+  });
+  return (pingpong ? 2 : 1) * col_lds_bytes(n, plan, C) + tw;
+}
+
+hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const ColArgs& a,
+                      int grid, hipStream_t st) {
   hipError_t e = hipErrorInvalidValue;
+  if (kind == 1) {
+    with_plan(n, plan, [&](auto p) {
+      using P = decltype(p);
+      const int lds = ((a.pingpong ? 2 : 1) * a.C * P::LDS_LINE + P::L * P::NTW + P::N) *
+                      (int)sizeof(float2);
+      const int threads = a.C * P::L;
+      if (dofwd && doinv)
+        hipLaunchKernelGGL((k_colb<P, true, true>), dim3(grid), dim3(threads), lds, st, a);
+      else if (dofwd)
+        hipLaunchKernelGGL((k_colb<P, true, false>), dim3(grid), dim3(threads), lds, st, a);
+      else
+        hipLaunchKernelGGL((k_colb<P, false, true>), dim3(grid), dim3(threads), lds, st, a);
+      e = hipGetLastError();
+    });
+    return e;
+  }
   with_plan(n, plan, [&](auto p) {
     using P = decltype(p);
     const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);

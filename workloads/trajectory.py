@@ -64,6 +64,25 @@ def harmonic_trajectory(struct, n_snap, dt_fs, seed, n_modes=256, omega_a_mev=35
         import torch
         out = torch.empty((n_snap, n, 3), dtype=torch.float32, device=device)
         tau_d = torch.from_numpy(tau.astype(np.complex64)).to(device)
+    if device is not None:
+        # same arithmetic with torch on the device (float64 phases, complex64 time products)
+        qd = torch.from_numpy(q).to(device)
+        thd = torch.from_numpy(theta).to(device)
+        ampd = torch.from_numpy(amp).to(device)
+        optd = torch.from_numpy(optical).to(device)
+        ed = torch.from_numpy(e).to(device)
+        r0d = torch.from_numpy(r0).to(device)
+        secd = torch.from_numpy(second).to(device)
+        for j0 in range(0, n, atom_chunk):
+            j1 = min(n, j0 + atom_chunk)
+            phase = 2.0 * np.pi * (r0d[j0:j1] @ qd.T) + thd[None, :]
+            sign = torch.where(optd[None, :] & secd[j0:j1, None], -1.0, 1.0).to(torch.float64)
+            coef = torch.complex(torch.cos(phase), torch.sin(phase)) * (ampd[None, :] * sign)
+            for c in range(3):
+                w = (coef * ed[None, :, c]).T.to(torch.complex64)
+                u = (tau_d @ w).real
+                out[:, j0:j1, c] = r0d[None, j0:j1, c].float() + u
+        return out
     for j0 in range(0, n, atom_chunk):
         j1 = min(n, j0 + atom_chunk)
         phase = 2.0 * np.pi * (r0[j0:j1] @ q.T) + theta[None, :]        # [n][M]
@@ -71,14 +90,8 @@ def harmonic_trajectory(struct, n_snap, dt_fs, seed, n_modes=256, omega_a_mev=35
         coef = (amp[None, :] * sign) * np.exp(1j * phase)               # [n][M]
         for c in range(3):
             w = coef * e[None, :, c]
-            if device is None:
-                u = (tau @ w.T).real                                    # [T][n]
-                out[:, j0:j1, c] = (r0[None, j0:j1, c] + u).astype(np.float32)
-            else:
-                wd = torch.from_numpy(w.T.astype(np.complex64)).to(device)
-                u = (tau_d @ wd).real
-                base = torch.from_numpy(r0[j0:j1, c].astype(np.float32)).to(device)
-                out[:, j0:j1, c] = base[None, :] + u
+            u = (tau @ w.T).real                                        # [T][n]
+            out[:, j0:j1, c] = (r0[None, j0:j1, c] + u).astype(np.float32)
     return out
 
 
