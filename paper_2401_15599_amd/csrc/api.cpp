@@ -714,9 +714,11 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
     int snaps_per = (int)std::max<size_t>(1, budget / (img * 8 * S));
     snaps_per = std::min(snaps_per, (int)n_snap);
     float2* vk = (float2*)workspace(ctx, "vk", (size_t)snaps_per * S * img * sizeof(float2));
+    void* arec = workspace(ctx, "atom_phase", (size_t)snaps_per * n_atoms * 24);
     for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
       const int nt = std::min(snaps_per, n_snap - t0);
       SfArgs a{};
+      a.arec = arec;
       a.xyz = xyz;
       a.order = ord;
       a.offsets = offs;
@@ -733,6 +735,8 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
       a.pref = (float)(2.0 * kPi * kA0 * kE4pe0 / (spec->lx * spec->ly));
       a.nmax = nmax;
       a.n_maps = nt * S;
+      // V(-k) = conj V(k) holds exactly when the band limit removes the Nyquist row and column
+      a.hermitian = (spec->bandlimit > 0.0 && spec->bandlimit < 1.0 && spec->ny >= 128) ? 1 : 0;
       timed_launch(ctx, st, "sf", 8.0 * img * nt * S, [&] {
         hip_check(launch_structure_factor(a, st), "structure-factor kernel");
       });

@@ -100,6 +100,8 @@ struct SfArgs {
   float kmax2;             // band limit in (1/A)^2 for |k|^2 (float comparison only for tile skip)
   const int* nmax;         // [nx] exact band-limit table
   int n_maps;
+  void* arec;              // workspace: 24-byte phase record per (snapshot of the pass, atom)
+  int hermitian;           // compute ky >= 0 only and write the conjugate reflection
 };
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st);
 hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hipStream_t st);

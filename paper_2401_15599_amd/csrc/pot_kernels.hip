@@ -130,20 +130,69 @@ __device__ __forceinline__ float form_factor(const float* f, float q2) {
 constexpr int kTile = 64;     // k-space tile edge (clamped to the grid)
 constexpr int kChunk = 64;    // atoms staged per LDS fill
 
-// one workgroup per (map, tile); 256 threads as 16 x 16, each owning 4 x 4 outputs
+// Per-atom phase records in CSR order: fixed-point fractional coordinates and the exact phase
+// factors of index 1 (the unit steps used to extend a block of phase factors).
+struct AtomPhase {
+  unsigned ux, uy;
+  float2 sx, sy;
+};
+
+__global__ __launch_bounds__(256) void k_atom_phase(const float* xyz, const int* order, int t0,
+                                                    int nt, int n_atoms, double lx, double ly,
+                                                    AtomPhase* rec) {
+  const long total = (long)nt * n_atoms;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+    const int tl = (int)(i / n_atoms), p = (int)(i % n_atoms);
+    const int aj = order[(size_t)(t0 + tl) * n_atoms + p];
+    AtomPhase r;
+    if (aj >= 0 && aj < n_atoms) {
+      const float* X = xyz + ((size_t)(t0 + tl) * n_atoms + aj) * 3;
+      r.ux = frac_fixed(X[0], lx);
+      r.uy = frac_fixed(X[1], ly);
+    } else {
+      r.ux = r.uy = 0u;   // positions past the binned atoms of this snapshot (never read)
+    }
+    r.sx = phase_factor(1, r.ux);
+    r.sy = phase_factor(1, r.uy);
+    rec[i] = r;
+  }
+}
+
+// One workgroup per (map, 64 x 64 k-tile), four wavefronts each owning a 32 x 32 quadrant.  The
+// complex outer-product sum over the atoms of a slice is a GEMM with K = atoms: per atom pair the
+// quadrant's real and imaginary parts take four v_mfma_f32_32x32x2f32 (A = y phases of the two
+// atoms down the quadrant's 32 ky, B = x phases across its 32 kx).  Phase tables for a chunk of
+// atoms are generated once per workgroup in LDS.
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int kSfChunk = 32;   // atoms per LDS fill
+
 __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
-  __shared__ float2 ex[kChunk][kTile];
-  __shared__ float2 ey[kChunk][kTile];
+  __shared__ float2 ex[kSfChunk][kTile + 1];
+  __shared__ float2 ey[kSfChunk][kTile + 1];
+  __shared__ AtomPhase arec[kSfChunk];
   __shared__ float ffs[kMaxSpecies * 12];
-  const int tx_n = (a.nx + kTile - 1) / kTile, ty_n = (a.ny + kTile - 1) / kTile;
+  // Hermitian mode (band limit on, ny >= 128): only storage rows [0, ny/2) are computed; row
+  // n > 0 is also written, conjugated, at (-n, -m); the Nyquist row is zero.
+  const int herm = a.hermitian;
+  const int tx_n = (a.nx + kTile - 1) / kTile;
+  const int ty_n = herm ? (a.ny / 2 + kTile - 1) / kTile : (a.ny + kTile - 1) / kTile;
   const int tiles = tx_n * ty_n;
   const int map = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   if (map >= a.n_maps) return;
   const int TW = min(kTile, a.nx), TH = min(kTile, a.ny);
   const int m0 = (tile % tx_n) * TW, n0 = (tile / tx_n) * TH;
   const int t = a.t0 + map / a.s_count, s = map % a.s_count;
-  const int tid = threadIdx.x, txi = tid & 15, tyi = tid >> 4;
+  const int tid = threadIdx.x;
   for (int i = tid; i < a.n_species * 12; i += 256) ffs[i] = a.ff[i];
+  float2* out = a.vk + (size_t)map * a.nx * a.ny;
+  auto put = [&](int n, int m, float2 v) {
+    out[(size_t)n * a.nx + m] = v;
+    if (herm && n > 0)
+      out[(size_t)(a.ny - n) * a.nx + (a.nx - m) % a.nx] = make_float2(v.x, -v.y);
+  };
+  if (herm && n0 == 0)
+    for (int m = m0 + tid; m < m0 + TW; m += 256)
+      out[(size_t)(a.ny / 2) * a.nx + m] = make_float2(0.f, 0.f);
 
   // does any k of this tile pass the band limit?  (exact integer table)
   int any = 0;
@@ -156,100 +205,105 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
     for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
   }
   any = __syncthreads_or(any);
-  float2* out = a.vk + (size_t)map * a.nx * a.ny;
   if (!any) {
-    for (int i = tid; i < TW * TH; i += 256)
-      out[(size_t)(n0 + i / TW) * a.nx + m0 + i % TW] = make_float2(0.f, 0.f);
+    for (int i = tid; i < TW * TH; i += 256) put(n0 + i / TW, m0 + i % TW, make_float2(0.f, 0.f));
     return;
   }
 
-  float2 vacc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) vacc[i][j] = make_float2(0.f, 0.f);
-
-  const float* X = a.xyz + (size_t)t * a.n_atoms * 3;
+  const int lane = tid & 63, w = tid >> 6, wy = w >> 1, wx = w & 1;
+  const int li = lane & 31, lk = lane >> 5;
+  v16f vr = {0}, vi = {0};
   const int* off = a.offsets + (size_t)t * (a.s_count * a.n_species + 1);
-  const int* ord = a.order + (size_t)t * a.n_atoms;
+  const AtomPhase* R = (const AtomPhase*)a.arec + (size_t)(t - a.t0) * a.n_atoms;
   for (int z = 0; z < a.n_species; ++z) {
     const int j0 = off[s * a.n_species + z], j1 = off[s * a.n_species + z + 1];
     if (j1 <= j0) continue;
-    float2 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
-    for (int c0 = j0; c0 < j1; c0 += kChunk) {
-      const int na = min(kChunk, j1 - c0);
+    v16f cr = {0}, ci = {0};
+    AtomPhase nrec;
+    if (tid < kSfChunk && j0 + tid < j1) nrec = R[j0 + tid];
+    for (int c0 = j0; c0 < j1; c0 += kSfChunk) {
+      const int na = min(kSfChunk, j1 - c0);
       __syncthreads();
-      for (int i = tid; i < kChunk * kTile; i += 256) {
-        const int at = i / kTile, k = i % kTile;
-        float2 fx = make_float2(0.f, 0.f), fy = make_float2(0.f, 0.f);
-        if (at < na) {
-          const int aj = ord[c0 + at];
-          if (k < TW) {
-            const int m = m0 + k, ms = m < a.nx / 2 ? m : m - a.nx;
-            fx = phase_factor(ms, frac_fixed(X[3 * aj], a.lx));
-          }
-          if (k < TH) {
-            const int n = n0 + k, ns = n < a.ny / 2 ? n : n - a.ny;
-            fy = phase_factor(ns, frac_fixed(X[3 * aj + 1], a.ly));
-          }
-        }
-        ex[at][k] = fx;
-        ey[at][k] = fy;
+      if (tid < kSfChunk) arec[tid] = nrec;   // this chunk's records (prefetched)
+      if (tid < kSfChunk) {                   // prefetch the next chunk of this species
+        const int nc = c0 + kSfChunk;
+        if (nc < j1 && nc + tid < j1) nrec = R[nc + tid];
       }
       __syncthreads();
-      for (int at = 0; at < na; ++at) {
-        float2 xv[4], yv[4];
+      // blocks of 8 consecutive indices: exact factor at the block start, then 7 steps of the
+      // atom's unit phase (aligned blocks never cross the +-N/2 wrap of the signed index)
+      for (int i = tid; i < 2 * kSfChunk * (kTile / 8); i += 256) {
+        const int axis = i / (kSfChunk * (kTile / 8));
+        const int rem = i % (kSfChunk * (kTile / 8));
+        const int at = rem / (kTile / 8), k0 = (rem % (kTile / 8)) * 8;
+        float2* dst = axis == 0 ? &ex[at][k0] : &ey[at][k0];
+        const int lim = axis == 0 ? TW : TH;
+        if (at >= na || k0 >= lim) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = ex[at][txi + 16 * j];
+          for (int q = 0; q < 8; ++q) dst[q] = make_float2(0.f, 0.f);
+          continue;
+        }
+        const int nn = axis == 0 ? a.nx : a.ny;
+        const int idx = (axis == 0 ? m0 : n0) + k0;
+        const int sidx = idx < nn / 2 ? idx : idx - nn;
+        const AtomPhase& ap = arec[at];
+        float2 f = phase_factor(sidx, axis == 0 ? ap.ux : ap.uy);
+        const float2 st = axis == 0 ? ap.sx : ap.sy;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) yv[i] = ey[at][tyi + 16 * i];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            acc[i][j].x = fmaf(yv[i].x, xv[j].x, fmaf(-yv[i].y, xv[j].y, acc[i][j].x));
-            acc[i][j].y = fmaf(yv[i].x, xv[j].y, fmaf(yv[i].y, xv[j].x, acc[i][j].y));
-          }
+        for (int q = 0; q < 8; ++q) {
+          dst[q] = f;
+          f = cmul(f, st);
+        }
+      }
+      __syncthreads();
+      const int npair = (na + 1) >> 1;
+      for (int p = 0; p < npair; ++p) {
+        const float2 yv = ey[2 * p + lk][32 * wy + li];
+        const float2 xv = ex[2 * p + lk][32 * wx + li];
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.x, xv.x, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.x, xv.y, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-yv.y, xv.y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.y, xv.x, ci, 0, 0, 0);
       }
     }
-    // multiply by the form factor of species z
+    // accumulator element r of this lane is (row (r&3) + 4 lk + 8 (r>>2), column li) of the quadrant
     const float* f = ffs + 12 * z;
+    const int m = m0 + 32 * wx + li, ms = m < a.nx / 2 ? m : m - a.nx;
+    const float kx = (float)ms / (float)a.lx;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int n = n0 + tyi + 16 * i, ns = n < a.ny / 2 ? n : n - a.ny;
+    for (int r = 0; r < 16; ++r) {
+      const int n = n0 + 32 * wy + (r & 3) + 4 * lk + 8 * (r >> 2), ns = n < a.ny / 2 ? n : n - a.ny;
       const float ky = (float)ns / (float)a.ly;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = m0 + txi + 16 * j, ms = m < a.nx / 2 ? m : m - a.nx;
-        const float kx = (float)ms / (float)a.lx;
-        const float fz = form_factor(f, kx * kx + ky * ky);
-        vacc[i][j].x = fmaf(fz, acc[i][j].x, vacc[i][j].x);
-        vacc[i][j].y = fmaf(fz, acc[i][j].y, vacc[i][j].y);
-      }
+      const float fz = form_factor(f, kx * kx + ky * ky);
+      vr[r] = fmaf(fz, cr[r], vr[r]);
+      vi[r] = fmaf(fz, ci[r], vi[r]);
     }
   }
+  const int tj = 32 * wx + li;
+  if (tj < TW) {
+    const int m = m0 + tj;
+    const int nm = a.nmax[m];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int ti = tyi + 16 * i;
-    if (ti >= TH) continue;
-    const int n = n0 + ti, ns = n < a.ny / 2 ? n : n - a.ny, an = ns < 0 ? -ns : ns;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int tj = txi + 16 * j;
-      if (tj >= TW) continue;
-      const int m = m0 + tj;
-      float2 v = (an <= a.nmax[m]) ? cscale(vacc[i][j], a.pref) : make_float2(0.f, 0.f);
-      out[(size_t)n * a.nx + m] = v;
+    for (int r = 0; r < 16; ++r) {
+      const int ti = 32 * wy + (r & 3) + 4 * lk + 8 * (r >> 2);
+      if (ti >= TH) continue;
+      const int n = n0 + ti, ns = n < a.ny / 2 ? n : n - a.ny, an = ns < 0 ? -ns : ns;
+      put(n, m, an <= nm ? make_float2(vr[r] * a.pref, vi[r] * a.pref) : make_float2(0.f, 0.f));
     }
   }
 }
 
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
-  const int tx_n = (a.nx + kTile - 1) / kTile, ty_n = (a.ny + kTile - 1) / kTile;
+  {
+    const long total = (long)(a.n_maps / a.s_count) * a.n_atoms;
+    long blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_atom_phase, dim3((unsigned)blocks), dim3(256), 0, st, a.xyz, a.order, a.t0,
+                       a.n_maps / a.s_count, a.n_atoms, a.lx, a.ly, (AtomPhase*)a.arec);
+  }
+  const int tx_n = (a.nx + kTile - 1) / kTile;
+  const int ty_n = a.hermitian ? (a.ny / 2 + kTile - 1) / kTile : (a.ny + kTile - 1) / kTile;
   const long blocks = (long)a.n_maps * tx_n * ty_n;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)blocks), dim3(256), 0, st, a);

@@ -105,11 +105,21 @@ def test_binning_bit_exact(case):
 # ------------------------------------------------------------------------------------------------
 # potentials
 
-@pytest.mark.parametrize("case", ["c1", "nonsquare", "no-bandlimit"])
+@pytest.mark.parametrize("case", ["c1", "nonsquare", "no-bandlimit", "half-plane-128",
+                                  "half-plane-256x128", "half-plane-off-128"])
 def test_potentials_match_oracle(case):
     if case == "c1":
         w = make_workload("c1", n_snap=3)
         spec, pos, species, ff = w, w.positions, w.species, w.ff
+    elif case.startswith("half-plane"):
+        # ny >= 128 with a band limit: only ky >= 0 is contracted, the rest is the conjugate
+        # reflection; without a band limit the full plane is contracted
+        nx, ny = (256, 128) if case.endswith("256x128") else (128, 128)
+        spec, pos, species = _random_specimen(nx, ny, nx * 0.2, ny * 0.25, [2.0, 1.5], 75, 2, 3,
+                                              outside=2)
+        ff = form_factor_table(["A", "B"])
+        if case.startswith("half-plane-off"):
+            spec.bandlimit = 0.0
     else:
         spec, pos, species = _random_specimen(64, 32, 12.0, 7.5, [2.0, 3.0, 1.5], 70, 2, 2,
                                               outside=3)
