@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-legs", action="store_true", help="skip the plain and adjoint legs")
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
+    p.add_argument("--calibrate", action="store_true",
+                   help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
     p.add_argument("--profile-slice-step", action="store_true",
                    help="short run for counter collection: one batched 512^2 multislice call of "
                         "the workload (8 snapshots) and a 1 GiB device copy as HBM calibration")
@@ -253,6 +255,12 @@ def main():
     import paper_2401_15599_amd as tw
 
     ctx = tw.context(0)
+    if args.calibrate:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tune = os.path.join(ROOT, "profiles", "tuning_gfx950.jsonl")
     if os.path.exists(tune):
         tw.tacaw_load_tuning(ctx, tune)
