@@ -94,11 +94,12 @@ def plain_leg(tw, ctx, ws, Vs):
     the 40-slice specimen, 4 probe positions, 32 snapshots."""
     import torch
     w = [x for x in ws if x.n_slices == 40][0] if any(x.n_slices == 40 for x in ws) else ws[-1]
-    V = Vs[ws.index(w)][:32].contiguous()
-    ex = torch.empty((32, 4, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+    nt = min(32, Vs[ws.index(w)].shape[0])
+    V = Vs[ws.index(w)][:nt].contiguous()
+    ex = torch.empty((nt, 4, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
     sp = tw.specimen_from(w)
     b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[:4])
-    steps = 32 * 4 * w.n_slices
+    steps = nt * 4 * w.n_slices
     out = {}
     for name, mode in (("plain", tw.MODE_PLAIN), ("batched", tw.MODE_BATCHED)):
         tw.tacaw_multislice(ctx, [tw.MsJob(sp, b, V, ex)], mode=mode)
@@ -109,7 +110,7 @@ def plain_leg(tw, ctx, ws, Vs):
             tw.tacaw_multislice(ctx, [tw.MsJob(sp, b, V, ex)], mode=mode)
         torch.cuda.synchronize()
         out[name] = steps * reps / (time.perf_counter() - t0)
-    return dict(subset=f"{w.name}: 4 positions x 32 snapshots x {w.n_slices} slices, 512^2",
+    return dict(subset=f"{w.name}: 4 positions x {nt} snapshots x {w.n_slices} slices, 512^2",
                 plain_slice_steps_per_s=out["plain"], batched_slice_steps_per_s=out["batched"],
                 batched_over_plain=out["batched"] / out["plain"])
 

@@ -258,7 +258,8 @@ const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n);
 /* ----------------------------------------------------------------------------------------------
  * Kernel timing instrumentation (for benchmarks and roofline reports).
  * With timing enabled, every slice-step launch (kinds "row", "col", "row_adj", "col_adj"), every
- * structure-factor launch ("sf"), potential inverse FFT ("pot_ifft") and periodogram ("pgram") is
+ * structure-factor launch ("sf"), potential inverse FFT ("pot_ifft"), periodogram ("pgram") and
+ * position-gradient contraction of tacaw_build_potentials_backward ("pos_grad", no byte model) is
  * bracketed by HIP events recorded on the stream it runs on, and its algorithmic HBM bytes are
  * recorded: x pass 8 (wave in) + 8 (wave out) [+ 8 checkpoint] [+ 8 stash] per image element and
  * wave, plus 4 per element of each V row read once for all probe positions (8 with dL/dV); y pass

@@ -188,9 +188,10 @@ class Context:
         self.handle = h
         self.device = device
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.tacaw_destroy):
+        # _destroy is bound at definition time: module globals may be gone at interpreter exit
         if getattr(self, "handle", None):
-            _lib.tacaw_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 

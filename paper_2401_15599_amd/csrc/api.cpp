@@ -775,11 +775,14 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
     const int cap = snaps_per * K + (int)(((long)snaps_per * n_atoms + 63) / 64) + 1;
     int4* chunks = (int4*)workspace(ctx, "chunks", (size_t)cap * sizeof(int4) + 16);
     int* count = (int*)(chunks + cap);
+    void* arec = workspace(ctx, "atom_phase", (size_t)snaps_per * n_atoms * 24);
     for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
       const int nt = std::min(snaps_per, n_snap - t0);
       hip_check(launch_fft2_real(spec->nx, spec->ny, grad_V + (size_t)t0 * S * img, gk, nt * S, st),
                 "gradient FFT");
       hip_check(launch_chunk_list(offs, t0, nt, S, n_species, chunks, cap, count, st), "chunk list");
+      hip_check(launch_atom_phase(xyz, ord, t0, nt, n_atoms, spec->lx, spec->ly, arec, st),
+                "atom phases");
       PgArgs a{};
       a.xyz = xyz;
       a.order = ord;
@@ -798,7 +801,11 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
       a.ly = spec->ly;
       a.pref = (float)(2.0 * kPi * kA0 * kE4pe0 / (spec->lx * spec->ly));
       a.nmax = nmax;
-      hip_check(launch_position_grad_chunks(a, chunks, cap, count, st), "position-gradient kernel");
+      a.arec = arec;
+      a.hermitian = (spec->bandlimit > 0.0 && spec->bandlimit < 1.0 && spec->ny >= 128) ? 1 : 0;
+      timed_launch(ctx, st, "pos_grad", 0.0, [&] {
+        hip_check(launch_position_grad_chunks(a, chunks, cap, count, st), "position-gradient kernel");
+      });
     }
   });
 }

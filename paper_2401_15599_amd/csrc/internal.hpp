@@ -114,7 +114,11 @@ struct PgArgs {
   double lx, ly;
   float pref;
   const int* nmax;
+  void* arec;              // per-atom phase records of the pass (CSR order)
+  int hermitian;           // visit ky >= 0 only (band limit on)
 };
+hipError_t launch_atom_phase(const float* xyz, const int* order, int t0, int nt, int n_atoms,
+                             double lx, double ly, void* rec, hipStream_t st);
 hipError_t launch_position_grad(const PgArgs& a, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 

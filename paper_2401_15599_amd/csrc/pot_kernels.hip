@@ -293,14 +293,22 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
   }
 }
 
+hipError_t launch_atom_phase(const float* xyz, const int* order, int t0, int nt, int n_atoms,
+                             double lx, double ly, void* rec, hipStream_t st) {
+  const long total = (long)nt * n_atoms;
+  long blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_atom_phase, dim3((unsigned)blocks), dim3(256), 0, st, xyz, order, t0, nt,
+                     n_atoms, lx, ly, (AtomPhase*)rec);
+  return hipGetLastError();
+}
+
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
   {
-    const long total = (long)(a.n_maps / a.s_count) * a.n_atoms;
-    long blocks = (total + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_atom_phase, dim3((unsigned)blocks), dim3(256), 0, st, a.xyz, a.order, a.t0,
-                       a.n_maps / a.s_count, a.n_atoms, a.lx, a.ly, (AtomPhase*)a.arec);
+    hipError_t e = launch_atom_phase(a.xyz, a.order, a.t0, a.n_maps / a.s_count, a.n_atoms, a.lx,
+                                     a.ly, a.arec, st);
+    if (e != hipSuccess) return e;
   }
   const int tx_n = (a.nx + kTile - 1) / kTile;
   const int ty_n = a.hermitian ? (a.ny / 2 + kTile - 1) / kTile : (a.ny + kTile - 1) / kTile;
@@ -311,118 +319,156 @@ hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// dL/d(x, y): one workgroup per (map, species-pure chunk of 64 atoms); loops over k tiles.
-// H(k) = conj(G(k)) pref M(k) f_Z(|k|);  dx_j = 2 pi Im sum_n ey_j(n) sum_m H(n,m) kx_m ex_j(m)
-//                                        dy_j = 2 pi Im sum_n ey_j(n) ky_n sum_m H(n,m) ex_j(m)
+// dL/d(x, y): one workgroup per (map, species-pure chunk of at most 64 atoms).
+// With H(k) = conj(G(k)) pref M(k) f_Z(|k|), G = DFT[dL/dV_s]:
+//   T[a][m]  = sum_n ey_a(n) H(n, m),   T'[a][m] = sum_n ey_a(n) ky_n H(n, m)      (MFMA, K = ky)
+//   dx_a = 2 pi Im sum_m T[a][m] kx_m ex_a(m),   dy_a = 2 pi Im sum_m T'[a][m] ex_a(m)
+// G is Hermitian (dL/dV is real), so the summand at -k is minus the conjugate of the one at k and
+// the imaginary parts agree: with the band limit on, rows ky > 0 are visited with weight 2 and the
+// row ky = 0 with weight 1.  Four wavefronts: (atom half) x (kx half) quadrants of 32 x 32.
 __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chunks,
                                                       const int* n_chunks) {
+  __shared__ float2 E[kChunk][kTile + 1];     // y phases during the ky loop, then x phases
   __shared__ float2 H[kTile][kTile + 1];
-  __shared__ float2 ex[kChunk][kTile + 1];
-  __shared__ float2 ey[kChunk][kTile + 1];
-  __shared__ float red[256][2];
+  __shared__ AtomPhase rec[kChunk];
+  __shared__ float red[4][32][2];
   if ((int)blockIdx.x >= *n_chunks) return;
-  const int4 ch = chunks[blockIdx.x];   // (map, first CSR index, count, species)
+  const int4 ch = chunks[blockIdx.x];          // (map, first CSR index, count, species)
   const int map = ch.x, c0 = ch.y, na = ch.z, z = ch.w;
-  const int t = a.t0 + map / a.s_count;
-  const int tid = threadIdx.x;
-  const int am = tid >> 2, nsub = tid & 3;   // atom within chunk, n subset (rows nsub + 4 i)
-  const float* X = a.xyz + (size_t)t * a.n_atoms * 3;
-  const int* ord = a.order + (size_t)t * a.n_atoms;
-  const float2* G = a.gk + (size_t)map * a.nx * a.ny;
+  const int tl = map / a.s_count, t = a.t0 + tl;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 31, lk = lane >> 5, wa = w >> 1, wk = w & 1;
+  const AtomPhase* R = (const AtomPhase*)a.arec + (size_t)tl * a.n_atoms;
+  if (tid < kChunk) {
+    AtomPhase r{0u, 0u, make_float2(1.f, 0.f), make_float2(1.f, 0.f)};
+    if (tid < na) r = R[c0 + tid];
+    rec[tid] = r;
+  }
   float f[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) f[i] = a.ff[12 * z + i];
+  const float2* G = a.gk + (size_t)map * a.nx * a.ny;
   const int TW = min(kTile, a.nx), TH = min(kTile, a.ny);
-  const int tx_n = a.nx / TW, ty_n = a.ny / TH;
-  float dx = 0.f, dy = 0.f;
-  for (int ty = 0; ty < ty_n; ++ty) {
-    const int n0 = ty * TH;
-    int minabs_n = 1 << 30;
-    for (int n = n0; n < n0 + TH; ++n) {
-      int ns = n < a.ny / 2 ? n : n - a.ny;
-      minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
+  const int herm = a.hermitian;
+  const int tx_n = a.nx / TW;
+  const int ty_n = herm ? (a.ny / 2 + TH - 1) / TH : a.ny / TH;
+  float sx[16], sy[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) { sx[r] = 0.f; sy[r] = 0.f; }
+
+  // fill E[atom][k] for k < lim with exp(-2 pi i idx(k0 + k) U), in blocks of 8 from one exact factor
+  auto fill_phases = [&](int axis, int k0, int lim, int nn) {
+    for (int i = tid; i < kChunk * (kTile / 8); i += 256) {
+      const int at = i / (kTile / 8), kb = (i % (kTile / 8)) * 8;
+      float2* dst = &E[at][kb];
+      if (at >= na || kb >= lim) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dst[q] = make_float2(0.f, 0.f);
+        continue;
+      }
+      const int idx = k0 + kb, sidx = idx < nn / 2 ? idx : idx - nn;
+      float2 ph = phase_factor(sidx, axis == 0 ? rec[at].ux : rec[at].uy);
+      const float2 st = axis == 0 ? rec[at].sx : rec[at].sy;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        dst[q] = ph;
+        ph = cmul(ph, st);
+      }
     }
-    for (int tx = 0; tx < tx_n; ++tx) {
-      const int m0 = tx * TW;
+  };
+
+  for (int tx = 0; tx < tx_n; ++tx) {
+    const int m0 = tx * TW;
+    v16f cr = {0}, ci = {0}, tr = {0}, ti = {0};
+    int used = 0;
+    for (int ty = 0; ty < ty_n; ++ty) {
+      const int n0 = ty * TH;
+      int minabs_n = 1 << 30;
+      for (int n = n0; n < n0 + TH; ++n) {
+        int ns = n < a.ny / 2 ? n : n - a.ny;
+        minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
+      }
       int any = 0;
       for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
       if (!__syncthreads_or(any)) continue;
+      used = 1;
       for (int i = tid; i < kTile * kTile; i += 256) {
         const int r = i / kTile, c = i % kTile;
         float2 h = make_float2(0.f, 0.f);
         if (r < TH && c < TW) {
           const int n = n0 + r, m = m0 + c;
           const int ns = n < a.ny / 2 ? n : n - a.ny, ms = m < a.nx / 2 ? m : m - a.nx;
-          if ((ns < 0 ? -ns : ns) <= a.nmax[m]) {
+          if ((ns < 0 ? -ns : ns) <= a.nmax[m] && (!herm || n < a.ny / 2)) {
             const float ky = (float)ns / (float)a.ly, kx = (float)ms / (float)a.lx;
-            const float w = a.pref * form_factor(f, kx * kx + ky * ky);
+            const float wgt = (herm && n > 0) ? 2.f : 1.f;
+            const float v = wgt * a.pref * form_factor(f, kx * kx + ky * ky);
             const float2 g = G[(size_t)n * a.nx + m];
-            h = make_float2(g.x * w, -g.y * w);
+            h = make_float2(g.x * v, -g.y * v);
           }
         }
         H[r][c] = h;
       }
-      for (int i = tid; i < kChunk * kTile; i += 256) {
-        const int at = i / kTile, k = i % kTile;
-        float2 fx = make_float2(0.f, 0.f), fy = make_float2(0.f, 0.f);
-        if (at < na) {
-          const int aj = ord[c0 + at];
-          if (k < TW) {
-            const int m = m0 + k, ms = m < a.nx / 2 ? m : m - a.nx;
-            fx = phase_factor(ms, frac_fixed(X[3 * aj], a.lx));
-          }
-          if (k < TH) {
-            const int n = n0 + k, ns = n < a.ny / 2 ? n : n - a.ny;
-            fy = phase_factor(ns, frac_fixed(X[3 * aj + 1], a.ly));
-          }
-        }
-        ex[at][k] = fx;
-        ey[at][k] = fy;
-      }
+      fill_phases(1, n0, TH, a.ny);
       __syncthreads();
-      if (am < na) {
-        float2 U[16], Ux[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) { U[i] = make_float2(0.f, 0.f); Ux[i] = U[i]; }
-        for (int c = 0; c < TW; ++c) {
-          const int m = m0 + c, ms = m < a.nx / 2 ? m : m - a.nx;
-          const float kx = (float)ms / (float)a.lx;
-          const float2 e = ex[am][c];
-          const float2 ek = make_float2(e.x * kx, e.y * kx);
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const float2 h = H[i * 4 + nsub][c];     // interleaved rows: no bank conflicts
-            U[i] = cadd(U[i], cmul(h, e));
-            Ux[i] = cadd(Ux[i], cmul(h, ek));
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = i * 4 + nsub;
-          if (r < TH) {
-            const int n = n0 + r, ns = n < a.ny / 2 ? n : n - a.ny;
-            const float ky = (float)ns / (float)a.ly;
-            const float2 e = ey[am][r];
-            dx += cmul(e, Ux[i]).y;
-            dy += ky * cmul(e, U[i]).y;
-          }
-        }
+      for (int p = 0; p < kTile / 2; ++p) {
+        const int k = 2 * p + lk;
+        const int n = n0 + k, ns = n < a.ny / 2 ? n : n - a.ny;
+        const float ky = (float)ns / (float)a.ly;
+        const float2 av = E[32 * wa + li][k];
+        const float2 bv = H[k][32 * wk + li];
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.y, ci, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x * ky, bv.x, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x * ky, bv.y, ti, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv.y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.x, ci, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y * ky, bv.y, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y * ky, bv.x, ti, 0, 0, 0);
       }
       __syncthreads();
     }
-  }
-  red[tid][0] = dx;
-  red[tid][1] = dy;
-  __syncthreads();
-  if (nsub == 0 && am < na) {
-    float sx = 0.f, sy = 0.f;
+    if (!used) continue;
+    // fold with the x phases of this kx tile
+    fill_phases(0, m0, TW, a.nx);
+    __syncthreads();
+    const int col = 32 * wk + li, m = m0 + col, ms = m < a.nx / 2 ? m : m - a.nx;
+    const float kx = (float)ms / (float)a.lx;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { sx += red[tid + k][0]; sy += red[tid + k][1]; }
-    const int aj = ord[c0 + am];
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * wa + (r & 3) + 4 * lk + 8 * (r >> 2);
+      const float2 e = E[row][col];
+      sx[r] += kx * (cr[r] * e.y + ci[r] * e.x);
+      sy[r] += tr[r] * e.y + ti[r] * e.x;
+    }
+    __syncthreads();
+  }
+  // sum over the 32 columns held by the lanes li of each half-wave
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      sx[r] += __shfl_xor(sx[r], o, 32);
+      sy[r] += __shfl_xor(sy[r], o, 32);
+    }
+  }
+  if (li == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = (r & 3) + 4 * lk + 8 * (r >> 2);
+      red[w][row][0] = sx[r];
+      red[w][row][1] = sy[r];
+    }
+  }
+  __syncthreads();
+  if (tid < na) {
+    const int h = tid >> 5, row = tid & 31;
+    const float dx = red[2 * h][row][0] + red[2 * h + 1][row][0];
+    const float dy = red[2 * h][row][1] + red[2 * h + 1][row][1];
+    const int aj = a.order[(size_t)t * a.n_atoms + c0 + tid];
     float* out = a.gxy + ((size_t)t * a.n_atoms + aj) * 2;
     const float two_pi = 6.283185307179586f;
-    out[0] = two_pi * sx;
-    out[1] = two_pi * sy;
+    out[0] = two_pi * dx;
+    out[1] = two_pi * dy;
   }
 }
 

@@ -265,10 +265,10 @@ def test_pipeline_c1_end_to_end():
 # ------------------------------------------------------------------------------------------------
 # gradients
 
-def _grad_problem(seed=0):
+def _grad_problem(seed=0, n=32):
     rng = np.random.default_rng(seed)
-    nx = ny = 32
-    lx, ly = 8.0, 7.0
+    nx = ny = n
+    lx, ly = 8.0 * n / 32, 7.0 * n / 32
     dz = np.array([2.0, 2.0, 2.0])
     n_at, T = 24, 16
     base = np.column_stack([rng.uniform(0, lx, n_at), rng.uniform(0, ly, n_at),
@@ -283,9 +283,10 @@ def _grad_problem(seed=0):
     return spec, beam, pos, species, form_factor_table(["A", "B"]), n_e, hop, dt, emask, target
 
 
-@pytest.mark.parametrize("stride", [1, 2])
-def test_gradients_match_oracle(stride):
-    spec, beam, pos, species, ff, n_e, hop, dt, emask, target = _grad_problem(1)
+@pytest.mark.parametrize("stride,n", [(1, 32), (2, 32), (2, 128)])
+def test_gradients_match_oracle(stride, n):
+    # n = 128 takes the half-plane path of the potential and position-gradient kernels
+    spec, beam, pos, species, ff, n_e, hop, dt, emask, target = _grad_problem(1, n)
     ref = o_adj.pipeline_gradient(pos, species, ff, spec, beam, n_e, hop, dt, 300.0, target, emask)
     tspec, tbeam = tw.specimen_from(spec), tw.Beam(100e3)
     xyz = _gpu(pos).requires_grad_(True)
