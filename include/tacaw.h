@@ -249,9 +249,15 @@ int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int
  * Synchronous (waits for the device).  Errors: TACAW_E_SIZE, TACAW_E_NOMEM, TACAW_E_HIP. */
 int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache_path,
                    void* stream);
-/* Load tuning choices previously written by tacaw_autotune (host, synchronous).
- * A missing file is not an error.  Errors: TACAW_E_ARG (malformed file). */
+/* Load tuning choices previously written by tacaw_autotune (host, synchronous).  One JSON object
+ * per line: {"n": grid, "row": x-pass plan, "col": y-pass plan, "C": columns per tile (power of
+ * two <= 64), "kind": y-pass kernel (0 staged, 1 workgroup-exchange block, 2 wave-per-column),
+ * "pp": ping-pong exchange buffers of kind 1 (0/1)}.  C is reduced at launch to what fits the
+ * grid, the workgroup and the LDS.  A missing file is not an error.
+ * Errors: TACAW_E_ARG (malformed file). */
 int tacaw_load_tuning(tacaw_ctx* ctx, const char* cache_path);
+/* Number of compiled FFT plans (radix chains and lanes per line) for grid size n, 0 if none. */
+int tacaw_plan_count(int32_t n);
 /* Current schedule for grid n as text ("row=<plan> col=<plan> C=<cols>"), for logging. */
 const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n);
 

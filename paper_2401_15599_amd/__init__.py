@@ -90,6 +90,7 @@ _SIGS = {
     "tacaw_autotune": ([_P, _I, _I, ctypes.c_char_p, _P], ctypes.c_int),
     "tacaw_load_tuning": ([_P, ctypes.c_char_p], ctypes.c_int),
     "tacaw_describe_schedule": ([_P, _I], ctypes.c_char_p),
+    "tacaw_plan_count": ([_I], ctypes.c_int),
     "tacaw_set_timing": ([_P, _I], ctypes.c_int),
     "tacaw_get_timing": ([_P, ctypes.c_char_p, ctypes.POINTER(KernelStats)], ctypes.c_int),
 }
@@ -341,6 +342,10 @@ def tacaw_autotune(ctx, n, n_waves, cache_path=None, stream=None):
 
 def tacaw_load_tuning(ctx, cache_path):
     _check(_lib.tacaw_load_tuning(ctx.handle, cache_path.encode()))
+
+
+def tacaw_plan_count(n):
+    return int(_lib.tacaw_plan_count(n))
 
 
 def tacaw_describe_schedule(ctx, n):

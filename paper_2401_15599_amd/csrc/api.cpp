@@ -341,6 +341,13 @@ Sched fit_cols(tacaw_ctx* c, int ny, Sched s, int nx) {
     while (s.C > 1 && s.C * L > 1024) s.C /= 2;
     if (s.pp && col_block_lds_bytes(ny, s.col_plan, s.C, 1) > c->max_lds) s.pp = 0;
     while (s.C > 1 && col_block_lds_bytes(ny, s.col_plan, s.C, s.pp) > c->max_lds) s.C /= 2;
+  } else if (s.col_kind == 2) {
+    while (s.C > 1 && (col_wave_threads(ny, s.col_plan, s.C) > 1024 ||
+                       col_wave_lds_bytes(ny, s.col_plan, s.C) > c->max_lds))
+      s.C /= 2;
+    if (col_wave_threads(ny, s.col_plan, s.C) > 1024 ||
+        col_wave_lds_bytes(ny, s.col_plan, s.C) > c->max_lds)
+      fail(TACAW_E_ARG, "wave-per-column y pass: no column count fits grid " + std::to_string(ny));
   } else {
     while (s.C > 1 && col_lds_bytes(ny, s.col_plan, s.C) > c->max_lds) s.C /= 2;
   }
@@ -491,7 +498,10 @@ struct Launcher {
     a.pingpong = sc.pp;
     const long tasks = (long)a.n_waves * (a.nx / a.C);
     // block kernel: one or two resident workgroups per CU (LDS bound); staged: up to 8
-    const long per_cu = sc.col_kind == 1 ? std::max(1, c->max_lds / std::max(1, col_block_lds_bytes(ny, sc.col_plan, sc.C, sc.pp))) : 8;
+    const long per_cu =
+        sc.col_kind == 1 ? std::max(1, c->max_lds / std::max(1, col_block_lds_bytes(ny, sc.col_plan, sc.C, sc.pp)))
+        : sc.col_kind == 2 ? std::max(1, c->max_lds / std::max(1, col_wave_lds_bytes(ny, sc.col_plan, sc.C)))
+                           : 8;
     long g = std::min<long>(tasks, (long)c->n_cu * per_cu);
     const double bytes = 16.0 * (double)a.nx * ny * a.n_waves;
     timed_launch(c, st, a.conj_prop ? "col_adj" : "col", bytes, [&] {
@@ -1124,9 +1134,12 @@ int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out) 
 static std::string sched_line(int n, const Sched& s) {
   std::ostringstream o;
   o << "row=" << plan_name(n, s.row_plan) << " col=" << plan_name(n, s.col_plan) << " C=" << s.C
-    << (s.col_kind == 1 ? " block" : " staged") << (s.pp ? " pingpong" : "");
+    << (s.col_kind == 1 ? " block" : s.col_kind == 2 ? " wave-per-column" : " staged")
+    << (s.col_kind == 1 && s.pp ? " pingpong" : "");
   return o.str();
 }
+
+int tacaw_plan_count(int32_t n) { return pow2_in(n, 16, 1024) ? n_plans(n) : 0; }
 
 const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n) {
   if (!ctx || !pow2_in(n, 16, 1024)) return "";
@@ -1157,7 +1170,8 @@ int tacaw_load_tuning(tacaw_ctx* ctx, const char* path) {
       s.col_kind = num("kind");
       s.pp = num("pp");
       if (!pow2_in(n, 16, 1024) || s.row_plan < 0 || s.row_plan >= n_plans(n) || s.col_plan < 0 ||
-          s.col_plan >= n_plans(n) || s.C < 1)
+          s.col_plan >= n_plans(n) || !pow2_in(s.C, 1, 64) || s.col_kind < 0 || s.col_kind > 2 ||
+          s.pp < 0 || s.pp > 1)
         fail(TACAW_E_ARG, "malformed tuning entry");
       ctx->sched[n] = s;
     }
@@ -1223,13 +1237,15 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
       if (ms < best_row) { best_row = ms; best.row_plan = rp; }
     }
     for (int cpn = 0; cpn < n_plans(n); ++cpn)
-      for (int kind = 0; kind < 2; ++kind)
+      for (int kind = 0; kind < 3; ++kind)
       for (int pp = 0; pp < (kind == 1 ? 2 : 1); ++pp)
       for (int C = 8; C <= 64; C *= 2) {
         if (C > n) continue;
         if (kind == 0 && col_lds_bytes(n, cpn, C) > ctx->max_lds) continue;
         if (kind == 1 && (C * plan_lanes(n, cpn) > 1024 ||
                           col_block_lds_bytes(n, cpn, C, pp) > ctx->max_lds)) continue;
+        if (kind == 2 && (col_wave_threads(n, cpn, C) > 1024 ||
+                          col_wave_lds_bytes(n, cpn, C) > ctx->max_lds)) continue;
         Sched sc = best;
         sc.col_plan = cpn;
         sc.C = C;

@@ -81,6 +81,9 @@ hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hip
 hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const ColArgs& a, int grid,
                       hipStream_t st);
 int col_block_lds_bytes(int n, int plan, int C, int pingpong);
+// kind 2: LDS-staged tile, one line per wavefront lane group, C * 64 / LINES threads
+int col_wave_lds_bytes(int n, int plan, int C);
+int col_wave_threads(int n, int plan, int C);
 int plan_lanes(int n, int plan);
 hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStream_t st);
 hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st);

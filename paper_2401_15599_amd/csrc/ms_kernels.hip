@@ -53,14 +53,34 @@ const char* plan_name(int n, int idx) {
   return names[base + idx];
 }
 
-__device__ __forceinline__ float2* pick_buf(const MsJobDev& J, int code, int wave, int s) {
+// Address spaces.  Wave data is accessed through global-address-space pointers: flat (generic)
+// accesses share the LDS completion counter, so every LDS wait inside a transform would also wait
+// for the prefetch of the next tile.  Job descriptors and task lists are read-only during a launch
+// and indexed uniformly, so they are read through the constant address space (scalar loads).
+// (The host compilation pass only type-checks kernel bodies; it sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL_AS __attribute__((address_space(1)))
+#define CONST_AS __attribute__((address_space(4)))
+#else
+#define GLOBAL_AS
+#define CONST_AS
+#endif
+typedef const CONST_AS MsJobDev CJob;
+
+template <class T> __device__ __forceinline__ GLOBAL_AS T* gp(T* p) { return (GLOBAL_AS T*)p; }
+__device__ __forceinline__ CJob& job_at(const MsJobDev* jobs, int i) { return ((CJob*)jobs)[i]; }
+template <class T> __device__ __forceinline__ T const_at(const T* base, int i) {
+  return ((const CONST_AS T*)base)[i];
+}
+
+__device__ __forceinline__ GLOBAL_AS float2* pick_buf(CJob& J, int code, int wave, int s) {
   size_t o = img_off(wave, J.nx, J.ny);
   switch (code) {
-    case BUF_W: return J.W + o;
-    case BUF_REC: return J.rec + o;
-    case BUF_ADJ: return J.adj + o;
-    case BUF_GEXIT: return const_cast<float2*>(J.gexit) + o;
-    default: return J.ckpt + img_off(wave * J.n_ck + s / J.ck_stride, J.nx, J.ny);
+    case BUF_W: return gp(J.W) + o;
+    case BUF_REC: return gp(J.rec) + o;
+    case BUF_ADJ: return gp(J.adj) + o;
+    case BUF_GEXIT: return gp(const_cast<float2*>(J.gexit)) + o;
+    default: return gp(J.ckpt) + img_off(wave * J.n_ck + s / J.ck_stride, J.nx, J.ny);
   }
 }
 
@@ -76,23 +96,24 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
 
-  const int ny = a.ny;
-  const long n_tasks = (long)a.n_groups * ny;
-  const long stride = (long)gridDim.x * kWaves * LINES;
-  for (long base = ((long)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
-    const long task = base + line;
+  const int ny = a.ny, ysh = __builtin_ctz(ny);
+  const int n_tasks = a.n_groups << ysh;
+  const int stride = (int)gridDim.x * kWaves * LINES;
+  for (int base = ((int)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
+    const int task = base + line;
     if (task >= n_tasks) continue;
-    const int g = (int)(task / ny), y = (int)(task % ny);
-    const int2 gr = a.groups[g];
-    const MsJobDev& J = a.jobs[gr.x];
+    const int g = task >> ysh, y = task & (ny - 1);
+    const int2 gr = const_at(a.groups, g);
+    CJob& J = job_at(a.jobs, gr.x);
     const int t = gr.y, s = a.s;
     const size_t row = (size_t)y * N;
-    const float* vrow = J.V + ((size_t)(t * J.S + s) * ny) * N + row;
+    const GLOBAL_AS float* vrow = gp(J.V) + ((size_t)(t * J.S + s) * ny) * N + row;
+    const float sigma = J.sigma;
     float2 tr[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       float sn, cs;
-      sincosf(J.sigma * vrow[l + L * j], &sn, &cs);
+      sincosf(sigma * vrow[l + L * j], &sn, &cs);
       tr[j] = make_float2(cs, sn);
     }
     float gacc[ADJ ? E : 1];
@@ -100,21 +121,22 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
 #pragma unroll
       for (int j = 0; j < E; ++j) gacc[j] = 0.f;
     }
-    for (int p = 0; p < J.P; ++p) {
-      const int w = t * J.P + p;
-      const float2* in = pick_buf(J, a.in_buf, w, s) + row;
+    const int P_ = J.P;
+    for (int p = 0; p < P_; ++p) {
+      const int w = t * P_ + p;
+      const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s) + row;
       float2 v[E];
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = in[l + L * j];
       if (!ADJ && a.store_ckpt) {
-        float2* ck = J.ckpt + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
+        GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j) ck[l + L * j] = v[j];
       }
       FFT<P>::template run<true>(v, tw, lds, l);          // psi_s (real space)
       if constexpr (!ADJ) {
         if (a.stash_slot >= 0) {
-          float2* st = J.stash + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
+          GLOBAL_AS float2* st = gp(J.stash) + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
 #pragma unroll
           for (int j = 0; j < E; ++j) st[l + L * j] = v[j];
         }
@@ -122,23 +144,23 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
         for (int j = 0; j < E; ++j) v[j] = cmul(v[j], tr[j]);
       } else {
         // v = chi_s (adjoint at the post-transmission point); psi_s from the stash
-        const float2* st = J.stash + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
+        const GLOBAL_AS float2* st = gp(J.stash) + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
           float2 tp = cmul(tr[j], st[l + L * j]);
-          gacc[j] -= J.sigma * (v[j].x * tp.y - v[j].y * tp.x);   // -sigma Im(conj(chi) t psi)
-          v[j] = cmulc(v[j], tr[j]);                               // conj(t) chi
+          gacc[j] -= sigma * (v[j].x * tp.y - v[j].y * tp.x);   // -sigma Im(conj(chi) t psi)
+          v[j] = cmulc(v[j], tr[j]);                             // conj(t) chi
         }
       }
       if (a.write_out) {
         FFT<P>::template run<false>(v, tw, lds, l);
-        float2* out = pick_buf(J, a.out_buf, w, s) + row;
+        GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j) out[l + L * j] = v[j];
       }
     }
     if constexpr (ADJ) {
-      float* grow = J.gV + ((size_t)(t * J.S + s) * ny) * N + row;
+      GLOBAL_AS float* grow = gp(J.gV) + ((size_t)(t * J.S + s) * ny) * N + row;
 #pragma unroll
       for (int j = 0; j < E; ++j) grow[l + L * j] = gacc[j];
     }
@@ -156,15 +178,15 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
   const int C = a.C, nx = a.nx;
-  const int tpi = nx / C;
-  const long n_tasks = (long)a.n_waves * tpi;
-  for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
-    const int4 wv = a.waves[task / tpi];
-    const int col0 = (int)(task % tpi) * C;
-    const MsJobDev& J = a.jobs[wv.x];
+  const int tsh = __builtin_ctz(nx / C), tmask = nx / C - 1;
+  const int n_tasks = a.n_waves << tsh;
+  for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    const int4 wv = const_at(a.waves, task >> tsh);
+    const int col0 = (task & tmask) * C;
+    CJob& J = job_at(a.jobs, wv.x);
     const int w = wv.y * J.P + wv.z, s = a.s;
-    const float2* in = pick_buf(J, a.in_buf, w, s);
-    float2* out = pick_buf(J, a.out_buf, w, s);
+    const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s);
+    GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s);
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
@@ -180,9 +202,9 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
         for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
         if constexpr (DOFWD) FFT<P>::template run<false>(v, tw, lds, l);
         const int m = col0 + c;
-        const int nm = J.nmax[m];
-        const float2 pxm = J.px[(size_t)s * nx + m];
-        const float2* pys = J.py + (size_t)s * N;
+        const int nm = gp(J.nmax)[m];
+        const float2 pxm = gp(J.px)[(size_t)s * nx + m];
+        const GLOBAL_AS float2* pys = gp(J.py) + (size_t)s * N;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
           const int n = l + L * j;
@@ -228,24 +250,25 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
   }
   const float2* tw = twl + l * NTW;
   int buf = 0;
-  const int tpi = nx / C, s = a.s;
-  const long n_tasks = (long)a.n_waves * tpi;
+  const int s = a.s;
+  const int tsh = __builtin_ctz(nx / C), tmask = nx / C - 1;
+  const int n_tasks = a.n_waves << tsh;
   float2 nxt[E];
   float2 nxt_px = make_float2(0.f, 0.f);
   int nxt_nm = -1;
   // uniform image base + per-lane 32-bit element offsets
-  auto load = [&](long tk) {
-    const int4 wv = a.waves[tk / tpi];
-    const MsJobDev& J = a.jobs[wv.x];
-    const float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s);
-    const int m = (int)(tk % tpi) * C + c;
+  auto load = [&](int tk) {
+    const int4 wv = const_at(a.waves, tk >> tsh);
+    CJob& J = job_at(a.jobs, wv.x);
+    const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s);
+    const int m = (tk & tmask) * C + c;
 #pragma unroll
     for (int j = 0; j < E; ++j) nxt[j] = in[(l + L * j) * nx + m];
-    nxt_px = J.px[s * nx + m];
-    nxt_nm = J.nmax[m];
+    nxt_px = gp(J.px)[s * nx + m];
+    nxt_nm = gp(J.nmax)[m];
   };
   int py_job = -1;
-  long task = blockIdx.x;
+  int task = blockIdx.x;
   if (task < n_tasks) load(task);
   for (; task < n_tasks; task += gridDim.x) {
     float2 v[E];
@@ -253,31 +276,137 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
     for (int j = 0; j < E; ++j) v[j] = nxt[j];
     const float2 pxm = nxt_px;
     const int nm = nxt_nm;
-    const int4 wv = a.waves[task / tpi];
-    const int m = (int)(task % tpi) * C + c;
+    const int4 wv = const_at(a.waves, task >> tsh);
+    const int m = (task & tmask) * C + c;
     if (wv.x != py_job) {                            // uniform branch
       __syncthreads();                               // previous tile's readers are done
-      const float2* pys = a.jobs[wv.x].py + s * N;
-      for (int i = threadIdx.x; i < N; i += blockDim.x) pyl[i] = pys[i];
+      const GLOBAL_AS float2* pys = gp(job_at(a.jobs, wv.x).py) + s * N;
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        float2 q = pys[i];
+        if (a.conj_prop) q.y = -q.y;
+        pyl[i] = q;
+      }
       __syncthreads();
       py_job = wv.x;
     }
-    if (task + gridDim.x < n_tasks) load(task + gridDim.x);
+    if (task + (int)gridDim.x < n_tasks) load(task + gridDim.x);
     if constexpr (DOFWD) FFT<P>::template run_block<false>(v, tw, reg0, reg1, l, buf);
+    {
+      // band-limited propagator (conjugated for the adjoint; pyl is stored conjugated then)
+      float2 pxs = cscale(pxm, a.scale);
+      if (a.conj_prop) pxs.y = -pxs.y;
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int n = l + L * j;
-      const int ns = n < N / 2 ? n : n - N;
-      float2 d = make_float2(0.f, 0.f);
-      if ((ns < 0 ? -ns : ns) <= nm) d = cmul(pxm, pyl[n]);
-      if (a.conj_prop) d.y = -d.y;
-      v[j] = cscale(cmul(v[j], d), a.scale);
+      for (int j = 0; j < E; ++j) {
+        const int n = l + L * j;
+        const int ns = n < N / 2 ? n : n - N;
+        float2 d = cmul(pxs, pyl[n]);
+        if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
+        v[j] = cmul(v[j], d);
+      }
     }
     if constexpr (DOINV) FFT<P>::template run_block<true>(v, tw, reg0, reg1, l, buf);
-    const MsJobDev& J = a.jobs[wv.x];
-    float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s);
+    CJob& J = job_at(a.jobs, wv.x);
+    GLOBAL_AS float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s);
 #pragma unroll
     for (int j = 0; j < E; ++j) out[(l + L * j) * nx + m] = v[j];
+  }
+}
+
+// y pass, wave-per-column variant: the tile of C columns is staged through LDS with coalesced row
+// segments (column stride 1 mod 16: conflict-free transposes); every wavefront then transforms
+// whole columns with wave-local exchanges (no barrier inside a transform).  The next tile is
+// prefetched into registers while the current one is transformed.  C * 64 / LINES threads.
+template <class P> constexpr int colw_max_threads() { return P::E > 8 ? 512 : 1024; }
+
+template <class P, bool DOFWD, bool DOINV>
+__global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE, NTW = P::NTW;
+  extern __shared__ float2 lds_mem[];
+  const int C = a.C, nx = a.nx;
+  const int nthr = blockDim.x;
+  float2* tile = lds_mem;
+  float2* twl = lds_mem + C * CS;                 // [L][NTW]
+  float2* pyl = twl + L * NTW;                    // [N]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int line = lane / L, l = lane % L;
+  const int c = wave * LINES + line;              // column of the tile owned by this line
+  if (threadIdx.x < L) {
+    float2 t[NTW];
+    PlanOps<P>::twiddles(t, threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < NTW; ++k) twl[threadIdx.x * NTW + k] = t[k];
+  }
+  const float2* tw = twl + l * NTW;
+  const int s = a.s;
+  const int tsh = __builtin_ctz(nx / C), tmask = nx / C - 1;
+  const int n_tasks = a.n_waves << tsh;
+  // staging: C * N elements per tile over C * 64 / LINES threads = E per thread; C is a power of 2
+  const int csh = __builtin_ctz(C), cmask = C - 1;
+  float2 nxt[E];
+  auto load = [&](int tk) {
+    const int4 wv = const_at(a.waves, tk >> tsh);
+    CJob& J = job_at(a.jobs, wv.x);
+    const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s) + (tk & tmask) * C;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int idx = (int)threadIdx.x + k * nthr;
+      nxt[k] = in[(idx >> csh) * nx + (idx & cmask)];
+    }
+  };
+  int py_job = -1;
+  int task = blockIdx.x;
+  if (task < n_tasks) load(task);
+  for (; task < n_tasks; task += gridDim.x) {
+    const int4 wv = const_at(a.waves, task >> tsh);
+    const int col0 = (task & tmask) * C;
+    __syncthreads();                                // previous tile fully stored from LDS
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int idx = (int)threadIdx.x + k * nthr;
+      tile[(idx & cmask) * CS + lds_pad(idx >> csh)] = nxt[k];
+    }
+    if (wv.x != py_job) {
+      const GLOBAL_AS float2* pys = gp(job_at(a.jobs, wv.x).py) + s * N;
+      for (int i = threadIdx.x; i < N; i += nthr) {
+        float2 q = pys[i];
+        if (a.conj_prop) q.y = -q.y;
+        pyl[i] = q;
+      }
+      py_job = wv.x;
+    }
+    if (task + (int)gridDim.x < n_tasks) load(task + gridDim.x);
+    __syncthreads();
+    CJob& J = job_at(a.jobs, wv.x);
+    if (c < C) {
+      const int m = col0 + c;
+      const int nm = gp(J.nmax)[m];
+      const float2 pxm = gp(J.px)[s * nx + m];
+      float2* reg = tile + c * CS;
+      float2 v[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = reg[lds_pad(l + L * j)];
+      if constexpr (DOFWD) FFT<P>::template run<false>(v, tw, reg, l);
+      float2 pxs = cscale(pxm, a.scale);
+      if (a.conj_prop) pxs.y = -pxs.y;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int n = l + L * j;
+        const int ns = n < N / 2 ? n : n - N;
+        float2 d = cmul(pxs, pyl[n]);
+        if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
+        v[j] = cmul(v[j], d);
+      }
+      if constexpr (DOINV) FFT<P>::template run<true>(v, tw, reg, l);
+#pragma unroll
+      for (int j = 0; j < E; ++j) reg[lds_pad(l + L * j)] = v[j];
+    }
+    __syncthreads();
+    GLOBAL_AS float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s) + col0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int idx = (int)threadIdx.x + k * nthr;
+      out[(idx >> csh) * nx + (idx & cmask)] = tile[(idx & cmask) * CS + lds_pad(idx >> csh)];
+    }
   }
 }
 
@@ -296,10 +425,10 @@ __global__ __launch_bounds__(kThreads) void k_probe_init(ColArgs a) {
   for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
     const int4 wv = a.waves[task / tpi];
     const int col0 = (int)(task % tpi) * C;
-    const MsJobDev& J = a.jobs[wv.x];
+    CJob& J = job_at(a.jobs, wv.x);
     const int w = wv.y * J.P + wv.z;
-    float2* out = pick_buf(J, a.out_buf, w, 0);
-    const double xp = J.pxy[2 * wv.z], yp = J.pxy[2 * wv.z + 1];
+    GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, 0);
+    const double xp = gp(J.pxy)[2 * wv.z], yp = gp(J.pxy)[2 * wv.z + 1];
     __syncthreads();
     for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
       const int c = cb + line;
@@ -307,7 +436,7 @@ __global__ __launch_bounds__(kThreads) void k_probe_init(ColArgs a) {
         float2* lds = tile + c * CS;
         const int m = col0 + c;
         const int ms = m < nx / 2 ? m : m - nx;
-        const int na = J.nap[m];
+        const int na = gp(J.nap)[m];
         const double kx = (double)ms / J.lx;
         float2 v[E];
 #pragma unroll
@@ -345,9 +474,9 @@ __global__ __launch_bounds__(kThreads) void k_plane_init(ColArgs a) {
   const int nx = a.nx;
   for (long wi = blockIdx.x; wi < a.n_waves; wi += gridDim.x) {
     const int4 wv = a.waves[wi];
-    const MsJobDev& J = a.jobs[wv.x];
+    CJob& J = job_at(a.jobs, wv.x);
     const int w = wv.y * J.P + wv.z;
-    float2* out = pick_buf(J, a.out_buf, w, 0);
+    GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, 0);
     const size_t n = (size_t)nx * J.ny;
     for (size_t i = threadIdx.x; i < n; i += kThreads)
       out[i] = make_float2((i % nx) == 0 ? J.scale_last : 0.f, 0.f);
@@ -476,6 +605,9 @@ void prepare_dynamic_lds(int max_bytes) {
         (void)hipFuncSetAttribute((const void*)k_colb<P, true, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_colb<P, true, false>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_colb<P, false, true>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colw<P, true, true>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colw<P, true, false>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colw<P, false, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, false>, (hipFuncAttribute)attr, max_bytes);
       });
@@ -497,9 +629,44 @@ int col_block_lds_bytes(int n, int plan, int C, int pingpong) {
   return (pingpong ? 2 : 1) * col_lds_bytes(n, plan, C) + tw;
 }
 
+int col_wave_lds_bytes(int n, int plan, int C) {
+  int b = 0;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    b = (C * P::LDS_LINE + P::L * P::NTW + P::N) * (int)sizeof(float2);
+  });
+  return b;
+}
+
+int col_wave_threads(int n, int plan, int C) {
+  int t = 0;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    t = (C / P::LINES) * 64;
+    // every wavefront must own LINES whole columns, within the kernel's launch bound
+    if (C % P::LINES != 0 || t > colw_max_threads<P>()) t = 1 << 30;
+  });
+  return t;
+}
+
 hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const ColArgs& a,
                       int grid, hipStream_t st) {
   hipError_t e = hipErrorInvalidValue;
+  if (kind == 2) {
+    with_plan(n, plan, [&](auto p) {
+      using P = decltype(p);
+      const int lds = col_wave_lds_bytes(n, plan, a.C);
+      const int threads = col_wave_threads(n, plan, a.C);
+      if (dofwd && doinv)
+        hipLaunchKernelGGL((k_colw<P, true, true>), dim3(grid), dim3(threads), lds, st, a);
+      else if (dofwd)
+        hipLaunchKernelGGL((k_colw<P, true, false>), dim3(grid), dim3(threads), lds, st, a);
+      else
+        hipLaunchKernelGGL((k_colw<P, false, true>), dim3(grid), dim3(threads), lds, st, a);
+      e = hipGetLastError();
+    });
+    return e;
+  }
   if (kind == 1) {
     with_plan(n, plan, [&](auto p) {
       using P = decltype(p);

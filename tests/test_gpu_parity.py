@@ -194,6 +194,47 @@ def test_multislice_uneven_batch_in_one_call():
             check(out.cpu().numpy(), ref, 1e-4)
 
 
+@pytest.mark.parametrize("n", [64, 256, 512])
+def test_every_fft_schedule_matches_oracle(n, tmp_path):
+    """Each compiled x-pass plan, y-pass plan, y-pass kernel kind and tile width gives the same
+    exit waves (same transform, different blocking); configurations whose tile cannot fit the
+    grid or the LDS are rejected before any launch."""
+    rng = np.random.default_rng(n)
+    S, T = 3, 2
+    spec = SimpleNamespace(nx=n, ny=n, lx=0.25 * n, ly=0.25 * n, dz=np.full(S, 1.8), z0=0.0,
+                           bandlimit=2.0 / 3.0)
+    beam = SimpleNamespace(probe=True, energy_ev=200e3, alpha_rad=0.025, defocus_a=0.0, cs_a=0.0,
+                           probe_xy=np.array([[0.1 * n, 0.13 * n], [0.17 * n, 0.05 * n]]))
+    V32 = rng.uniform(0.0, 1.5, size=(T, S, n, n)).astype(np.float32)
+    ref = o_ms.exit_waves(V32.astype(np.float64), spec, beam)
+    jspec, jbeam, V = tw.specimen_from(spec), tw.beam_from(beam), _gpu(V32)
+    n_plans = tw.tacaw_plan_count(n)
+    assert n_plans >= 1
+    variants = [(r, 0, 1, 16, 1) for r in range(n_plans)]
+    variants += [(0, c, k, C, pp) for c in range(n_plans) for k in (0, 1, 2)
+                 for C in (8, 16, 32, 64) for pp in ((0, 1) if k == 1 else (0,))]
+    ran = 0
+    for i, (r, c, k, C, pp) in enumerate(variants):
+        f = tmp_path / f"tune{i}.json"
+        f.write_text(f'{{"n": {n}, "row": {r}, "col": {c}, "C": {C}, "kind": {k}, "pp": {pp}}}\n')
+        cx = tw.Context(0)
+        tw.tacaw_load_tuning(cx, str(f))
+        exit = torch.empty((T, 2, n, n), dtype=torch.complex64, device=DEV)
+        try:
+            tw.tacaw_multislice(cx, [tw.MsJob(jspec, jbeam, V, exit)], mode=tw.MODE_BATCHED)
+        except tw.TacawError as e:
+            assert k == 2 and "no column count fits" in str(e), (r, c, k, C, pp, str(e))
+            continue
+        got = exit.cpu().numpy()
+        for t in range(T):
+            for p in range(2):
+                e = rel_l2(got[t, p], ref[t, p])
+                assert e <= 1e-4, f"{tw.tacaw_describe_schedule(cx, n)}: rel-L2 {e:.3e}"
+        ran += 1
+        del cx
+    assert ran >= len(variants) // 2
+
+
 def test_batched_graph_replay_is_stable():
     w = make_workload("c1", n_snap=3)
     V, _ = o_pot.potentials(w.positions, w.species, w.ff, w)
