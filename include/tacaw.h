@@ -120,7 +120,10 @@ int tacaw_bin_atoms(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap, 
  *   V_s(r) = Re sum_k V_s(k) exp(+2 pi i k.r) on the grid r = (x Lx/nx, y Ly/ny),
  *   f_Z(q) = sum_i a_i/(q^2 + b_i) + sum_i c_i exp(-d_i q^2),  2 pi a0 e = 47.8777 V Angstrom^2,
  *   M(k) = 1 when kx^2 + ky^2 < (bandlimit * kN)^2 (float64), else 0 (M = 1 if bandlimit <= 0).
- * The paper computes phi(q, tau) "by a standard multislice method"; this is that textbook potential.
+ * The paper obtains the exit waves with ordinary multislice; this is that method's textbook potential.
+ * The contraction over atoms runs on the matrix cores, by default with every phase factor split
+ * into fp16 high and low parts (three f16 products per term, fp32 accumulation, error below
+ * 2^-22 per unit phase product); tacaw_set_potential_precision selects plain fp32 operands.
  *   ff        host [n_species][12]: a1,b1,a2,b2,a3,b3,c1,d1,c2,d2,c3,d3 (q in 1/Angstrom)
  *   V         dev out [n_snap][S][ny][nx] float (V Angstrom)
  *   n_outside dev out [n_snap] int32 or NULL (as in tacaw_bin_atoms)
@@ -279,6 +282,10 @@ typedef struct {
   double algo_bytes;
 } tacaw_kernel_stats;
 int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable);
+/* Structure-factor operand precision for tacaw_build_potentials on this context:
+ * 1 (default) fp16 hi/lo split on v_mfma_f32_32x32x16_f16, 0 fp32 v_mfma_f32_32x32x2f32.
+ * Errors: TACAW_E_ARG (other values). */
+int tacaw_set_potential_precision(tacaw_ctx* ctx, int32_t split16);
 int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out);
 
 #ifdef __cplusplus

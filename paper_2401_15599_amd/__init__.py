@@ -92,6 +92,7 @@ _SIGS = {
     "tacaw_describe_schedule": ([_P, _I], ctypes.c_char_p),
     "tacaw_plan_count": ([_I], ctypes.c_int),
     "tacaw_set_timing": ([_P, _I], ctypes.c_int),
+    "tacaw_set_potential_precision": ([_P, _I], ctypes.c_int),
     "tacaw_get_timing": ([_P, ctypes.c_char_p, ctypes.POINTER(KernelStats)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -350,6 +351,10 @@ def tacaw_plan_count(n):
 
 def tacaw_describe_schedule(ctx, n):
     return _lib.tacaw_describe_schedule(ctx.handle, n).decode()
+
+
+def tacaw_set_potential_precision(ctx, split16):
+    _check(_lib.tacaw_set_potential_precision(ctx.handle, int(split16)))
 
 
 def tacaw_set_timing(ctx, enable):

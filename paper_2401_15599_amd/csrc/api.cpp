@@ -198,6 +198,7 @@ struct tacaw_ctx {
     double bytes;
   };
   bool timing = false;
+  int sf_split16 = 1;
   std::vector<Timed> timed;
   std::vector<hipEvent_t> ev_pool;
 
@@ -324,12 +325,25 @@ void validate_beam(const tacaw_beam* b) {
 Sched schedule_for(tacaw_ctx* c, int n) {
   auto it = c->sched.find(n);
   if (it != c->sched.end()) return it->second;
+  // built-in choices: tacaw_autotune on an MI355X over 1 GiB batches of waves per grid size
+  // {n, row plan, column plan, C, kind, pp}
+  static const int table[][6] = {{16, 1, 1, 16, 1, 1},  {32, 0, 0, 16, 2, 0},  {64, 0, 0, 64, 1, 0},
+                                 {128, 0, 0, 32, 1, 0}, {256, 0, 1, 32, 2, 0}, {512, 0, 0, 16, 1, 1},
+                                 {1024, 0, 0, 8, 2, 0}};
   Sched s;
   s.row_plan = 0;
   s.col_plan = 0;
   s.col_kind = 1;
   s.pp = 1;
   s.C = 16;   // 128-byte row segments
+  for (const auto& e : table)
+    if (e[0] == n) {
+      s.row_plan = e[1];
+      s.col_plan = e[2];
+      s.C = e[3];
+      s.col_kind = e[4];
+      s.pp = e[5];
+    }
   return s;
 }
 
@@ -747,6 +761,7 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
       a.n_maps = nt * S;
       // V(-k) = conj V(k) holds exactly when the band limit removes the Nyquist row and column
       a.hermitian = (spec->bandlimit > 0.0 && spec->bandlimit < 1.0 && spec->ny >= 128) ? 1 : 0;
+      a.split16 = ctx->sf_split16;
       timed_launch(ctx, st, "sf", 8.0 * img * nt * S, [&] {
         hip_check(launch_structure_factor(a, st), "structure-factor kernel");
       });
@@ -1102,6 +1117,14 @@ int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable) {
   return guarded([&] {
     use_device(ctx);
     ctx->timing = enable != 0;
+  });
+}
+
+int tacaw_set_potential_precision(tacaw_ctx* ctx, int32_t split16) {
+  return guarded([&] {
+    if (!ctx) fail(TACAW_E_ARG, "null context");
+    if (split16 != 0 && split16 != 1) fail(TACAW_E_ARG, "split16 must be 0 or 1");
+    ctx->sf_split16 = split16;
   });
 }
 

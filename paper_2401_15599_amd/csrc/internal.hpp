@@ -105,6 +105,7 @@ struct SfArgs {
   int n_maps;
   void* arec;              // workspace: 24-byte phase record per (snapshot of the pass, atom)
   int hermitian;           // compute ky >= 0 only and write the conjugate reflection
+  int split16;             // fp16 hi/lo split operands on the f16 matrix cores (else fp32 MFMA)
 };
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st);
 hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hipStream_t st);

@@ -122,12 +122,23 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
       for (int j = 0; j < E; ++j) gacc[j] = 0.f;
     }
     const int P_ = J.P;
+    // the next position's row is loaded while this one is transformed
+    float2 nv[E];
+    {
+      const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, t * P_, s) + row;
+#pragma unroll
+      for (int j = 0; j < E; ++j) nv[j] = in[l + L * j];
+    }
     for (int p = 0; p < P_; ++p) {
       const int w = t * P_ + p;
-      const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s) + row;
       float2 v[E];
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = in[l + L * j];
+      for (int j = 0; j < E; ++j) v[j] = nv[j];
+      if (p + 1 < P_) {
+        const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w + 1, s) + row;
+#pragma unroll
+        for (int j = 0; j < E; ++j) nv[j] = in[l + L * j];
+      }
       if (!ADJ && a.store_ckpt) {
         GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
 #pragma unroll

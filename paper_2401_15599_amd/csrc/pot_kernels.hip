@@ -132,10 +132,11 @@ constexpr int kChunk = 64;    // atoms staged per LDS fill
 
 // Per-atom phase records in CSR order: fixed-point fractional coordinates and the exact phase
 // factors of index 1 (the unit steps used to extend a block of phase factors).
-struct AtomPhase {
+struct AtomPhase {   // 24 bytes: fixed-point fractional x, y and unit phase steps
   unsigned ux, uy;
   float2 sx, sy;
 };
+static_assert(sizeof(AtomPhase) == 24 && alignof(AtomPhase) == 8, "phase record layout");
 
 __global__ __launch_bounds__(256) void k_atom_phase(const float* xyz, const int* order, int t0,
                                                     int nt, int n_atoms, double lx, double ly,
@@ -159,17 +160,35 @@ __global__ __launch_bounds__(256) void k_atom_phase(const float* xyz, const int*
 }
 
 // One workgroup per (map, 64 x 64 k-tile), four wavefronts each owning a 32 x 32 quadrant.  The
-// complex outer-product sum over the atoms of a slice is a GEMM with K = atoms: per atom pair the
-// quadrant's real and imaginary parts take four v_mfma_f32_32x32x2f32 (A = y phases of the two
-// atoms down the quadrant's 32 ky, B = x phases across its 32 kx).  Phase tables for a chunk of
-// atoms are generated once per workgroup in LDS.
+// complex outer-product sum over the atoms of a slice is a GEMM with K = atoms (A = y phases down
+// the quadrant's 32 ky, B = x phases across its 32 kx).  Phase tables for a chunk of atoms are
+// generated once per workgroup in LDS.
+//   SPLIT = false: fp32 operands, four v_mfma_f32_32x32x2f32 per atom pair.
+//   SPLIT = true:  every phase component p is split as p = hi + lo with hi = fp16(p) and
+//                  lo = fp16(p - hi); the products hi*hi + hi*lo + lo*hi are accumulated in fp32
+//                  by v_mfma_f32_32x32x16_f16 (the dropped lo*lo term is below 2^-22 for unit
+//                  phases), twelve MFMAs per 16 atoms.
 typedef float v16f __attribute__((ext_vector_type(16)));
-constexpr int kSfChunk = 32;   // atoms per LDS fill
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+constexpr int kSfChunk = 32;   // atoms per phase-table fill
+constexpr int kSfBatch = 256;  // atom records staged per LDS batch (the next batch is in flight)
+constexpr int kRowH = 40;      // halves per (component, k) row of a split table: 32 atoms + pad
+// rows 8 apart would fall in the same LDS banks (8 x 80 bytes); every group of 8 rows starts a
+// further 64 bytes on, so that the generator's half-wave stores (16 atom pairs x 2 row groups) and
+// the operand reads (8 rows x 16 bytes per pass) are conflict-free
+__device__ __forceinline__ int split_row(int r) { return r * kRowH + (r >> 3) * 32; }
+constexpr int kTabH = kTile * kRowH + (kTile / 8) * 32;   // halves per (axis, component) table
 
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
-  __shared__ float2 ex[kSfChunk][kTile + 1];
-  __shared__ float2 ey[kSfChunk][kTile + 1];
-  __shared__ AtomPhase arec[kSfChunk];
+  // fp32 tables ex/ey [atom][k] (float2) or split tables [axis][component][k][atom] (fp16)
+  constexpr int kBytesF32 = 2 * kSfChunk * (kTile + 1) * (int)sizeof(float2);
+  constexpr int kBytesF16 = 2 * 4 * kTabH * (int)sizeof(_Float16);
+  __shared__ __attribute__((aligned(16))) char tables[SPLIT ? kBytesF16 : kBytesF32];
+  float2 (*ex)[kTile + 1] = reinterpret_cast<float2 (*)[kTile + 1]>(tables);
+  float2 (*ey)[kTile + 1] = reinterpret_cast<float2 (*)[kTile + 1]>(tables) + kSfChunk;
+  _Float16* tb = reinterpret_cast<_Float16*>(tables);   // [axis][component][split_row(k) + atom]
+  __shared__ AtomPhase batch[kSfBatch];   // phase records of up to kSfBatch atoms of one species
   __shared__ float ffs[kMaxSpecies * 12];
   // Hermitian mode (band limit on, ny >= 128): only storage rows [0, ny/2) are computed; row
   // n > 0 is also written, conjugated, at (-n, -m); the Nyquist row is zero.
@@ -219,51 +238,139 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
     const int j0 = off[s * a.n_species + z], j1 = off[s * a.n_species + z + 1];
     if (j1 <= j0) continue;
     v16f cr = {0}, ci = {0};
-    AtomPhase nrec;
-    if (tid < kSfChunk && j0 + tid < j1) nrec = R[j0 + tid];
+    // the next batch's records travel in registers as three 8-byte words (a struct held in a
+    // local variable would go through scratch memory and wait for the load at once)
+    const uint2* Rw = reinterpret_cast<const uint2*>(R);
+    uint2* bw = reinterpret_cast<uint2*>(batch);
+    uint2 nr0 = make_uint2(0u, 0u), nr1 = nr0, nr2 = nr0;
+    if (j0 + tid < j1) {
+      nr0 = Rw[3 * (j0 + tid)];
+      nr1 = Rw[3 * (j0 + tid) + 1];
+      nr2 = Rw[3 * (j0 + tid) + 2];
+    }
     for (int c0 = j0; c0 < j1; c0 += kSfChunk) {
       const int na = min(kSfChunk, j1 - c0);
-      __syncthreads();
-      if (tid < kSfChunk) arec[tid] = nrec;   // this chunk's records (prefetched)
-      if (tid < kSfChunk) {                   // prefetch the next chunk of this species
-        const int nc = c0 + kSfChunk;
-        if (nc < j1 && nc + tid < j1) nrec = R[nc + tid];
+      const int bi = (c0 - j0) % kSfBatch;    // chunk offset in the staged batch
+      __syncthreads();                        // previous chunk's tables (and batch) are consumed
+      if (bi == 0) {
+        bw[3 * tid] = nr0;                    // this batch (loaded one batch ahead)
+        bw[3 * tid + 1] = nr1;
+        bw[3 * tid + 2] = nr2;
+        const int nb = c0 + kSfBatch + tid;   // prefetch the next batch of this species
+        if (nb < j1) {
+          nr0 = Rw[3 * nb];
+          nr1 = Rw[3 * nb + 1];
+          nr2 = Rw[3 * nb + 2];
+        }
+        __syncthreads();
       }
-      __syncthreads();
+      const AtomPhase* arec = batch + bi;
       // blocks of 8 consecutive indices: exact factor at the block start, then 7 steps of the
       // atom's unit phase (aligned blocks never cross the +-N/2 wrap of the signed index)
-      for (int i = tid; i < 2 * kSfChunk * (kTile / 8); i += 256) {
-        const int axis = i / (kSfChunk * (kTile / 8));
-        const int rem = i % (kSfChunk * (kTile / 8));
-        const int at = rem / (kTile / 8), k0 = (rem % (kTile / 8)) * 8;
-        float2* dst = axis == 0 ? &ex[at][k0] : &ey[at][k0];
-        const int lim = axis == 0 ? TW : TH;
-        if (at >= na || k0 >= lim) {
+      if constexpr (!SPLIT) {
+        for (int i = tid; i < 2 * kSfChunk * (kTile / 8); i += 256) {
+          const int axis = i / (kSfChunk * (kTile / 8));
+          const int rem = i % (kSfChunk * (kTile / 8));
+          const int at = rem / (kTile / 8), k0 = (rem % (kTile / 8)) * 8;
+          float2* dst = axis == 0 ? &ex[at][k0] : &ey[at][k0];
+          const int lim = axis == 0 ? TW : TH;
+          if (at >= na || k0 >= lim) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) dst[q] = make_float2(0.f, 0.f);
-          continue;
+            for (int q = 0; q < 8; ++q) dst[q] = make_float2(0.f, 0.f);
+            continue;
+          }
+          const int nn = axis == 0 ? a.nx : a.ny;
+          const int idx = (axis == 0 ? m0 : n0) + k0;
+          const int sidx = idx < nn / 2 ? idx : idx - nn;
+          const AtomPhase& ap = arec[at];
+          float2 f = phase_factor(sidx, axis == 0 ? ap.ux : ap.uy);
+          const float2 st = axis == 0 ? ap.sx : ap.sy;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            dst[q] = f;
+            f = cmul(f, st);
+          }
         }
+      } else {
+        // one item per thread: (axis, block of 8 k, atom pair); components stored as packed
+        // (atom 2p, atom 2p+1) half pairs
+        const int axis = tid >> 7, k0 = ((tid >> 4) & 7) * 8, pair = tid & 15;
+        const int lim = axis == 0 ? TW : TH;
         const int nn = axis == 0 ? a.nx : a.ny;
         const int idx = (axis == 0 ? m0 : n0) + k0;
         const int sidx = idx < nn / 2 ? idx : idx - nn;
-        const AtomPhase& ap = arec[at];
-        float2 f = phase_factor(sidx, axis == 0 ? ap.ux : ap.uy);
-        const float2 st = axis == 0 ? ap.sx : ap.sy;
+        float2 f[2], st[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int at = 2 * pair + u;
+          if (at < na && k0 < lim) {
+            const AtomPhase& ap = arec[at];
+            f[u] = phase_factor(sidx, axis == 0 ? ap.ux : ap.uy);
+            st[u] = axis == 0 ? ap.sx : ap.sy;
+          } else {
+            f[u] = make_float2(0.f, 0.f);
+            st[u] = make_float2(0.f, 0.f);
+          }
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          dst[q] = f;
-          f = cmul(f, st);
+          float c[4][2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const _Float16 rh = (_Float16)f[u].x, ih = (_Float16)f[u].y;
+            c[0][u] = f[u].x;
+            c[1][u] = f[u].y;
+            c[2][u] = f[u].x - (float)rh;
+            c[3][u] = f[u].y - (float)ih;
+            f[u] = cmul(f[u], st[u]);
+          }
+#pragma unroll
+          for (int comp = 0; comp < 4; ++comp) {
+            typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+            h2 v = {(_Float16)c[comp][0], (_Float16)c[comp][1]};
+            *reinterpret_cast<h2*>(tb + (axis * 4 + comp) * kTabH + split_row(k0 + q) + 2 * pair) = v;
+          }
         }
       }
       __syncthreads();
-      const int npair = (na + 1) >> 1;
-      for (int p = 0; p < npair; ++p) {
-        const float2 yv = ey[2 * p + lk][32 * wy + li];
-        const float2 xv = ex[2 * p + lk][32 * wx + li];
-        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.x, xv.x, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.x, xv.y, ci, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-yv.y, xv.y, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.y, xv.x, ci, 0, 0, 0);
+      if constexpr (!SPLIT) {
+        const int npair = (na + 1) >> 1;
+        for (int p = 0; p < npair; ++p) {
+          const float2 yv = ey[2 * p + lk][32 * wy + li];
+          const float2 xv = ex[2 * p + lk][32 * wx + li];
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.x, xv.x, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.x, xv.y, ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-yv.y, xv.y, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.y, xv.x, ci, 0, 0, 0);
+        }
+      } else {
+        const _Float16* ty = tb + 4 * kTabH + split_row(32 * wy + li);
+        const _Float16* tx = tb + split_row(32 * wx + li);
+        for (int b = 0; 16 * b < na; ++b) {
+          const int kb = 16 * b + 8 * lk;
+          const v8h yrh = *reinterpret_cast<const v8h*>(ty + kb);
+          const v8h yih = *reinterpret_cast<const v8h*>(ty + kTabH + kb);
+          const v8h yrl = *reinterpret_cast<const v8h*>(ty + 2 * kTabH + kb);
+          const v8h yil = *reinterpret_cast<const v8h*>(ty + 3 * kTabH + kb);
+          const v8h xrh = *reinterpret_cast<const v8h*>(tx + kb);
+          const v8h xih = *reinterpret_cast<const v8h*>(tx + kTabH + kb);
+          const v8h xrl = *reinterpret_cast<const v8h*>(tx + 2 * kTabH + kb);
+          const v8h xil = *reinterpret_cast<const v8h*>(tx + 3 * kTabH + kb);
+          const v8h nyih = -yih, nyil = -yil;
+          // Re += yr xr - yi xi,  Im += yr xi + yi xr  (each as hi*hi + hi*lo + lo*hi)
+          cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xrh, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xih, ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xrl, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xil, ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrl, xrh, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrl, xih, ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(nyih, xih, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(yih, xrh, ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(nyih, xil, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(yih, xrl, ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(nyil, xih, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(yil, xrh, ci, 0, 0, 0);
+        }
       }
     }
     // accumulator element r of this lane is (row (r&3) + 4 lk + 8 (r>>2), column li) of the quadrant
@@ -314,7 +421,10 @@ hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
   const int ty_n = a.hermitian ? (a.ny / 2 + kTile - 1) / kTile : (a.ny + kTile - 1) / kTile;
   const long blocks = (long)a.n_maps * tx_n * ty_n;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  if (a.split16)
+    hipLaunchKernelGGL(k_structure_factor<true>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_structure_factor<false>, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

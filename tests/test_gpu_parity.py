@@ -105,9 +105,10 @@ def test_binning_bit_exact(case):
 # ------------------------------------------------------------------------------------------------
 # potentials
 
+@pytest.mark.parametrize("split16", [1, 0])
 @pytest.mark.parametrize("case", ["c1", "nonsquare", "no-bandlimit", "half-plane-128",
                                   "half-plane-256x128", "half-plane-off-128"])
-def test_potentials_match_oracle(case):
+def test_potentials_match_oracle(case, split16):
     if case == "c1":
         w = make_workload("c1", n_snap=3)
         spec, pos, species, ff = w, w.positions, w.species, w.ff
@@ -127,7 +128,9 @@ def test_potentials_match_oracle(case):
         if case == "no-bandlimit":
             spec.bandlimit = 0.0
     V = torch.empty((pos.shape[0], len(spec.dz), spec.ny, spec.nx), dtype=torch.float32, device=DEV)
-    tw.tacaw_build_potentials(ctx(), tw.specimen_from(spec), _gpu(pos), _gpu(species), ff, V)
+    cx = tw.Context(0)
+    tw.tacaw_set_potential_precision(cx, split16)
+    tw.tacaw_build_potentials(cx, tw.specimen_from(spec), _gpu(pos), _gpu(species), ff, V)
     ref, _ = o_pot.potentials(pos, species, ff, spec)
     check(V.cpu().numpy(), ref, 1e-5)
 
