@@ -123,6 +123,21 @@ std::vector<int> aperture_table(const tacaw_specimen& s, const tacaw_beam& b) {
   });
 }
 
+// Largest |signed kx index| of a column that keeps some ky.  The kernels skip the columns m with
+// kxb < m < nx - kxb; a table whose kept columns are not exactly the others (never the case for
+// a disk) gets nx/2, which skips nothing.
+int band_columns(const std::vector<int>& nmax) {
+  const int nx = (int)nmax.size();
+  int kxb = -1;
+  for (int m = 0; m < nx; ++m)
+    if (nmax[m] >= 0) kxb = std::max(kxb, m < nx / 2 ? m : nx - m);
+  for (int m = 0; m < nx; ++m) {
+    const bool inside = m <= kxb || m >= nx - kxb;
+    if (inside != (nmax[m] >= 0)) return nx / 2;
+  }
+  return std::max(kxb, 0);
+}
+
 // number of grid points kept by a column-limit table
 long count_kept(const std::vector<int>& t, int ny) {
   long c = 0;
@@ -378,6 +393,7 @@ struct ClassPlan {
   std::vector<long> group_wave_prefix;   // waves in groups [0, g)
   std::vector<int4> plane_waves, probe_waves;
   int Smax = 0;
+  int kxb = 0;                     // widest band of the class's jobs
 };
 
 int active_prefix(const std::vector<int>& S_sorted_desc, int s) {
@@ -420,7 +436,11 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
     d.ckpt = (float2*)J.ckpt;
     d.px = upload_vec(c, propagator_axis(S.nx, S.lx, lam, S.dz, S.n_slices), st, "px");
     d.py = upload_vec(c, propagator_axis(S.ny, S.ly, lam, S.dz, S.n_slices), st, "py");
-    d.nmax = upload_vec(c, bandlimit_table(S), st, "bl");
+    {
+      const std::vector<int> bl = bandlimit_table(S);
+      d.nmax = upload_vec(c, bl, st, "bl");
+      d.kxb = band_columns(bl);
+    }
     long n_ap = 1;
     if (B.kind == TACAW_PROBE) {
       std::vector<int> ap = aperture_table(S, B);
@@ -464,6 +484,7 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
   for (int j = 0; j < n_jobs; ++j) {
     ClassPlan& cp = b.classes[class_of[{b.jobs[j].nx, b.jobs[j].ny}]];
     for (int t = 0; t < b.jobs[j].T; ++t) cp.groups.push_back(make_int2(j, t));
+    cp.kxb = std::max(cp.kxb, b.jobs[j].kxb);
   }
   for (auto& cp : b.classes) {
     std::stable_sort(cp.groups.begin(), cp.groups.end(), [&](int2 a, int2 x) {
@@ -491,7 +512,8 @@ struct Launcher {
   tacaw_ctx* c;
   hipStream_t st;
   // waves: number of waves the launch covers (for the byte model only)
-  void row(int n, const Sched& sc, bool adj, RowArgs a, long waves) {
+  // kxb: the class's widest band (algorithmic bytes count the band-limited columns only)
+  void row(int n, const Sched& sc, bool adj, RowArgs a, long waves, int kxb) {
     if (a.n_groups <= 0) return;
     const int lines = row_lines_per_wave(n, sc.row_plan);
     const long tasks = (long)a.n_groups * a.ny;
@@ -499,25 +521,41 @@ struct Launcher {
     g = std::min<long>(g, (long)c->n_cu * 8);
     // bytes per image element: wave in 8, out 8, checkpoint 8, stash 8; per V row 4 (+4 for dL/dV)
     const double img = (double)n * a.ny;
-    double per_wave = 8.0 + (a.write_out ? 8.0 : 0.0) + (a.store_ckpt ? 8.0 : 0.0) +
-                      (a.stash_slot >= 0 ? 8.0 : 0.0);
+    const double band = (double)std::min(n, 2 * kxb + 1) / n;
+    double per_wave = 8.0 * (a.band_in ? band : 1.0) +
+                      (a.write_out ? 8.0 * (a.band_out ? band : 1.0) : 0.0) +
+                      (a.store_ckpt ? 8.0 : 0.0) + (a.stash_slot >= 0 ? 8.0 : 0.0);
     double bytes = img * (per_wave * waves + (adj ? 8.0 : 4.0) * a.n_groups);
     timed_launch(c, st, adj ? "row_adj" : "row", bytes, [&] {
       hip_check(launch_row(n, sc.row_plan, adj, a, (int)std::max<long>(g, 1), st), "row kernel");
     });
   }
-  void col(int ny, const Sched& sc, bool f, bool i, ColArgs a) {
+  // all_tiles: the output is read by the caller (exit waves), so every column is written
+  void col(int ny, const Sched& sc, bool f, bool i, ColArgs a, int kxb, bool all_tiles) {
     if (a.n_waves <= 0) return;
     a.C = sc.C;
     a.pingpong = sc.pp;
-    const long tasks = (long)a.n_waves * (a.nx / a.C);
+    const int tpi = a.nx / a.C;
+    a.tiles_lo = a.tiles_hi = 0;
+    if (!all_tiles && kxb < a.nx / 2) {
+      const int lo = std::min(tpi, kxb / a.C + 1);
+      const int hi = tpi - (a.nx - kxb) / a.C;
+      if (lo + hi < tpi) {
+        a.tiles_lo = lo;
+        a.tiles_hi = hi;
+      }
+    }
+    const int tiles = (a.tiles_lo + a.tiles_hi) > 0 ? a.tiles_lo + a.tiles_hi : tpi;
+    const long tasks = (long)a.n_waves * tiles;
     // block kernel: one or two resident workgroups per CU (LDS bound); staged: up to 8
     const long per_cu =
         sc.col_kind == 1 ? std::max(1, c->max_lds / std::max(1, col_block_lds_bytes(ny, sc.col_plan, sc.C, sc.pp)))
         : sc.col_kind == 2 ? std::max(1, c->max_lds / std::max(1, col_wave_lds_bytes(ny, sc.col_plan, sc.C)))
                            : 8;
     long g = std::min<long>(tasks, (long)c->n_cu * per_cu);
-    const double bytes = 16.0 * (double)a.nx * ny * a.n_waves;
+    // columns outside the band are never read; they are written only when all_tiles is set
+    const double nband = std::min(a.nx, 2 * kxb + 1);
+    const double bytes = 8.0 * (nband + (all_tiles ? a.nx : nband)) * ny * a.n_waves;
     timed_launch(c, st, a.conj_prop ? "col_adj" : "col", bytes, [&] {
       hip_check(launch_col(ny, sc.col_plan, sc.col_kind, f, i, a, (int)std::max<long>(g, 1), st),
                 "column kernel");
@@ -564,7 +602,9 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ra.stash_slot = -1;
         ra.write_out = 1;
         ra.ny = cp.ny;
-        L.row(cp.nx, rs, false, ra, active_prefix(wS, s));
+        ra.band_in = s > 0 ? 1 : 0;   // the initial wave is not band-limited
+        ra.band_out = 1;
+        L.row(cp.nx, rs, false, ra, active_prefix(wS, s), cp.kxb);
         const int n_mid = active_prefix(wS, s + 1), n_all = active_prefix(wS, s);
         ColArgs ca{};
         ca.jobs = b.jobs_dev;
@@ -578,13 +618,13 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
           ca.waves = waves;
           ca.n_waves = n_mid;
           ca.scale = (float)(1.0 / ((double)cp.nx * cp.ny));
-          L.col(cp.ny, cs, true, true, ca);
+          L.col(cp.ny, cs, true, true, ca, cp.kxb, false);
         }
         if (n_all > n_mid) {
           ca.waves = waves + n_mid;
           ca.n_waves = n_all - n_mid;
           ca.scale = (float)(1.0 / std::sqrt((double)cp.nx * cp.ny));
-          L.col(cp.ny, cs, true, false, ca);
+          L.col(cp.ny, cs, true, false, ca, cp.kxb, true);   // exit waves
         }
       }
     };
@@ -934,7 +974,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
         ca.out_buf = BUF_ADJ;
         ca.conj_prop = 1;
         ca.scale = scale_last;
-        L.col(cp.ny, cs, false, true, ca);
+        L.col(cp.ny, cs, false, true, ca, cp.kxb, false);
         const int nck = (S + ckpt_stride - 1) / ckpt_stride;
         for (int c = nck - 1; c >= 0; --c) {
           const int s0 = c * ckpt_stride, s1 = std::min(S, s0 + ckpt_stride);
@@ -950,7 +990,9 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
             ra.stash_slot = s - s0;
             ra.write_out = (s < s1 - 1) ? 1 : 0;
             ra.ny = cp.ny;
-            L.row(cp.nx, rs, false, ra, nw);
+            ra.band_in = s > 0 ? 1 : 0;
+            ra.band_out = 1;
+            L.row(cp.nx, rs, false, ra, nw, cp.kxb);
             if (s < s1 - 1) {
               ColArgs fa = ca;
               fa.s = s;
@@ -958,7 +1000,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
               fa.out_buf = BUF_REC;
               fa.conj_prop = 0;
               fa.scale = scale_mid;
-              L.col(cp.ny, cs, true, true, fa);
+              L.col(cp.ny, cs, true, true, fa, cp.kxb, false);
             }
           }
           for (int s = s1 - 1; s >= s0; --s) {
@@ -973,7 +1015,9 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
             ra.stash_slot = s - s0;
             ra.write_out = s > 0 ? 1 : 0;
             ra.ny = cp.ny;
-            L.row(cp.nx, rs, true, ra, nw);
+            ra.band_in = 1;    // adjoint states leave the adjoint y pass band-limited
+            ra.band_out = 1;
+            L.row(cp.nx, rs, true, ra, nw, cp.kxb);
             if (s > 0) {
               ColArgs aa = ca;
               aa.s = s - 1;
@@ -981,7 +1025,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
               aa.out_buf = BUF_ADJ;
               aa.conj_prop = 1;
               aa.scale = scale_mid;
-              L.col(cp.ny, cs, true, true, aa);
+              L.col(cp.ny, cs, true, true, aa, cp.kxb, false);
             }
           }
         }
@@ -1253,7 +1297,7 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
         ra.stash_slot = -1;
         ra.write_out = 1;
         ra.ny = n;
-        L.row(n, sc, false, ra, (long)cp.waves.size());
+        L.row(n, sc, false, ra, (long)cp.waves.size(), n / 2);
       });
       if (std::getenv("TACAW_TUNE_VERBOSE"))
         std::fprintf(stderr, "[tune] n=%d row plan %s: %.3f ms\n", n, plan_name(n, rp), ms / 5);
@@ -1285,7 +1329,7 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
           ca.C = C;
           ca.nx = n;
           ca.scale = 1.0f / (float)img;
-          L.col(n, sc, true, true, ca);
+          L.col(n, sc, true, true, ca, n / 2, true);
         });
         if (std::getenv("TACAW_TUNE_VERBOSE"))
           std::fprintf(stderr, "[tune] n=%d col plan %s kind=%d pp=%d C=%d: %.3f ms\n", n,

@@ -28,6 +28,8 @@ struct MsJobDev {
   const float2* gexit;     // [T][P][ny][nx]
   float* gV;               // [T][S][ny][nx]
   int T, P, S, nx, ny;
+  int kxb;                 // band-limited columns: kx index m is kept by some ky iff
+                           // m <= kxb or m >= nx - kxb (nx/2 without a band limit)
   int ck_stride, n_ck, stash_k;
   float sigma;
   float scale_mid, scale_last, scale_probe;
@@ -50,6 +52,8 @@ struct RowArgs {
   int stash_slot;          // >= 0: store psi_s (real space) into stash slot
   int write_out;           // 0: skip the forward x-transform and the store
   int ny;                  // rows per image (all jobs of a launch share nx, ny)
+  int band_in;             // the input is zero in the columns outside the band: not read
+  int band_out;            // the consumer ignores columns outside the band: not written
 };
 
 struct ColArgs {
@@ -63,6 +67,11 @@ struct ColArgs {
   float scale;             // 1/(nx ny), 1/sqrt(nx ny), ...
   int nx;                  // columns per image (all jobs of a launch share nx, ny)
   int pingpong;            // block kernel: two LDS exchange regions (one barrier per exchange)
+  // Column tiles visited per wave: the first tiles_lo and the last tiles_hi of nx / C (both 0: all).
+  // Tiles left out hold only columns outside every job's band; they are neither read nor written.
+  // Inside visited tiles, a column outside its job's band is taken as zero (its output is zero
+  // whatever the input, since M vanishes on the whole column).
+  int tiles_lo, tiles_hi;
 };
 
 // plain batched 2-D transforms of contiguous images (potential build, position gradient)

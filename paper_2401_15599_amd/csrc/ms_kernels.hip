@@ -84,6 +84,28 @@ __device__ __forceinline__ GLOBAL_AS float2* pick_buf(CJob& J, int code, int wav
   }
 }
 
+// *p when c holds, else zero (the load is not issued for lanes where c fails)
+__device__ __forceinline__ float2 load_if(const GLOBAL_AS float2* p, bool c) {
+  float2 x = make_float2(0.f, 0.f);
+  if (c) x = *p;
+  return x;
+}
+
+// column (or row element) index m of an n-point axis inside the job's band
+__device__ __forceinline__ bool in_band(int m, int kxb, int n) { return m <= kxb || m >= n - kxb; }
+
+// y-pass task -> (wave index, first column): tiles_lo tiles from the start of each wave's columns,
+// then tiles_hi from the end (all tiles when both are 0)
+__device__ __forceinline__ int col_tiles_per_wave(const ColArgs& a, int tpi) {
+  return (a.tiles_lo + a.tiles_hi) > 0 ? a.tiles_lo + a.tiles_hi : tpi;
+}
+__device__ __forceinline__ void col_task(const ColArgs& a, int task, int tpw, int tpi, int& wi,
+                                         int& col0) {
+  wi = task / tpw;
+  const int jt = task - wi * tpw;
+  col0 = (jt < a.tiles_lo || a.tiles_hi == 0 ? jt : jt + tpi - a.tiles_lo - a.tiles_hi) * a.C;
+}
+
 // ------------------------------------------------------------------------------------------------
 // x pass
 template <class P, bool ADJ>
@@ -122,22 +144,21 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
       for (int j = 0; j < E; ++j) gacc[j] = 0.f;
     }
     const int P_ = J.P;
-    // the next position's row is loaded while this one is transformed
-    float2 nv[E];
-    {
-      const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, t * P_, s) + row;
+    // band: element x of a row (a kx column of W) outside the job's band is zero on input (not
+    // read) and of no use on output (not written) when band_in / band_out say so
+    const int kxb = J.kxb;
+    // bit j: element l + L j is inside the band
+    unsigned inb = 0;
 #pragma unroll
-      for (int j = 0; j < E; ++j) nv[j] = in[l + L * j];
-    }
+    for (int j = 0; j < E; ++j) inb |= (in_band(l + L * j, kxb, N) ? 1u : 0u) << j;
+    const unsigned rmask = a.band_in ? inb : ~0u, wmask = a.band_out ? inb : ~0u;
     for (int p = 0; p < P_; ++p) {
       const int w = t * P_ + p;
       float2 v[E];
+      {
+        const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s) + row;
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = nv[j];
-      if (p + 1 < P_) {
-        const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w + 1, s) + row;
-#pragma unroll
-        for (int j = 0; j < E; ++j) nv[j] = in[l + L * j];
+        for (int j = 0; j < E; ++j) v[j] = load_if(in + l + L * j, (rmask >> j) & 1u);
       }
       if (!ADJ && a.store_ckpt) {
         GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
@@ -167,7 +188,8 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
         FFT<P>::template run<false>(v, tw, lds, l);
         GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s) + row;
 #pragma unroll
-        for (int j = 0; j < E; ++j) out[l + L * j] = v[j];
+        for (int j = 0; j < E; ++j)
+          if ((wmask >> j) & 1u) out[l + L * j] = v[j];
       }
     }
     if constexpr (ADJ) {
@@ -189,19 +211,22 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
   const int C = a.C, nx = a.nx;
-  const int tsh = __builtin_ctz(nx / C), tmask = nx / C - 1;
-  const int n_tasks = a.n_waves << tsh;
+  const int tpi = nx / C, tpw = col_tiles_per_wave(a, tpi);
+  const int n_tasks = a.n_waves * tpw;
   for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
-    const int4 wv = const_at(a.waves, task >> tsh);
-    const int col0 = (task & tmask) * C;
+    int wi, col0;
+    col_task(a, task, tpw, tpi, wi, col0);
+    const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
     const int w = wv.y * J.P + wv.z, s = a.s;
+    const int kxb = J.kxb;
     const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s);
     GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s);
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      tile[c * CS + lds_pad(r)] = in[(size_t)r * nx + col0 + c];
+      tile[c * CS + lds_pad(r)] =
+          load_if(in + (size_t)r * nx + col0 + c, in_band(col0 + c, kxb, nx));
     }
     __syncthreads();
     for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
@@ -262,19 +287,22 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
   const float2* tw = twl + l * NTW;
   int buf = 0;
   const int s = a.s;
-  const int tsh = __builtin_ctz(nx / C), tmask = nx / C - 1;
-  const int n_tasks = a.n_waves << tsh;
+  const int tpi = nx / C, tpw = col_tiles_per_wave(a, tpi);
+  const int n_tasks = a.n_waves * tpw;
   float2 nxt[E];
   float2 nxt_px = make_float2(0.f, 0.f);
   int nxt_nm = -1;
-  // uniform image base + per-lane 32-bit element offsets
+  // uniform image base + per-lane 32-bit element offsets; a column outside the band reads zeros
   auto load = [&](int tk) {
-    const int4 wv = const_at(a.waves, tk >> tsh);
+    int wi, col0;
+    col_task(a, tk, tpw, tpi, wi, col0);
+    const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
     const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s);
-    const int m = (tk & tmask) * C + c;
+    const int m = col0 + c;
+    const bool inb = in_band(m, J.kxb, nx);
 #pragma unroll
-    for (int j = 0; j < E; ++j) nxt[j] = in[(l + L * j) * nx + m];
+    for (int j = 0; j < E; ++j) nxt[j] = load_if(in + (l + L * j) * nx + m, inb);
     nxt_px = gp(J.px)[s * nx + m];
     nxt_nm = gp(J.nmax)[m];
   };
@@ -287,8 +315,10 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
     for (int j = 0; j < E; ++j) v[j] = nxt[j];
     const float2 pxm = nxt_px;
     const int nm = nxt_nm;
-    const int4 wv = const_at(a.waves, task >> tsh);
-    const int m = (task & tmask) * C + c;
+    int wi, col0;
+    col_task(a, task, tpw, tpi, wi, col0);
+    const int4 wv = const_at(a.waves, wi);
+    const int m = col0 + c;
     if (wv.x != py_job) {                            // uniform branch
       __syncthreads();                               // previous tile's readers are done
       const GLOBAL_AS float2* pys = gp(job_at(a.jobs, wv.x).py) + s * N;
@@ -349,27 +379,31 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
   }
   const float2* tw = twl + l * NTW;
   const int s = a.s;
-  const int tsh = __builtin_ctz(nx / C), tmask = nx / C - 1;
-  const int n_tasks = a.n_waves << tsh;
+  const int tpi = nx / C, tpw = col_tiles_per_wave(a, tpi);
+  const int n_tasks = a.n_waves * tpw;
   // staging: C * N elements per tile over C * 64 / LINES threads = E per thread; C is a power of 2
   const int csh = __builtin_ctz(C), cmask = C - 1;
   float2 nxt[E];
   auto load = [&](int tk) {
-    const int4 wv = const_at(a.waves, tk >> tsh);
+    int wi, col0;
+    col_task(a, tk, tpw, tpi, wi, col0);
+    const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
-    const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s) + (tk & tmask) * C;
+    const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s) + col0;
+    const int kxb = J.kxb;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int idx = (int)threadIdx.x + k * nthr;
-      nxt[k] = in[(idx >> csh) * nx + (idx & cmask)];
+      nxt[k] = load_if(in + (idx >> csh) * nx + (idx & cmask), in_band(col0 + (idx & cmask), kxb, nx));
     }
   };
   int py_job = -1;
   int task = blockIdx.x;
   if (task < n_tasks) load(task);
   for (; task < n_tasks; task += gridDim.x) {
-    const int4 wv = const_at(a.waves, task >> tsh);
-    const int col0 = (task & tmask) * C;
+    int wi, col0;
+    col_task(a, task, tpw, tpi, wi, col0);
+    const int4 wv = const_at(a.waves, wi);
     __syncthreads();                                // previous tile fully stored from LDS
 #pragma unroll
     for (int k = 0; k < E; ++k) {

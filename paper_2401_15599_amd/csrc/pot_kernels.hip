@@ -164,12 +164,13 @@ __global__ __launch_bounds__(256) void k_atom_phase(const float* xyz, const int*
 // the quadrant's 32 ky, B = x phases across its 32 kx).  Phase tables for a chunk of atoms are
 // generated once per workgroup in LDS.
 //   SPLIT = false: fp32 operands, four v_mfma_f32_32x32x2f32 per atom pair.
-//   SPLIT = true:  every phase component p is split as p = hi + lo with hi = fp16(p) and
-//                  lo = fp16(p - hi); the products hi*hi + hi*lo + lo*hi are accumulated in fp32
+//   SPLIT = true:  every phase component p is split as p = hi + lo with hi = fp16(p) (rounded
+//                  toward zero) and lo = fp16(p - hi); hi*hi + hi*lo + lo*hi are accumulated in fp32
 //                  by v_mfma_f32_32x32x16_f16 (the dropped lo*lo term is below 2^-22 for unit
 //                  phases), twelve MFMAs per 16 atoms.
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __fp16 h2 __attribute__((ext_vector_type(2)));   // the packing builtin's type
 constexpr int kSfChunk = 32;   // atoms per phase-table fill
 constexpr int kSfBatch = 256;  // atom records staged per LDS batch (the next batch is in flight)
 constexpr int kRowH = 40;      // halves per (component, k) row of a split table: 32 atoms + pad
@@ -312,24 +313,22 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
             st[u] = make_float2(0.f, 0.f);
           }
         }
+        // hi = fp16 of p rounded toward zero (packed for the atom pair), lo = fp16(p - hi); p - hi
+        // is exact in fp32 and |lo| < one fp16 ulp of p
+        _Float16* row = tb + axis * 4 * kTabH + 2 * pair;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          float c[4][2];
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const _Float16 rh = (_Float16)f[u].x, ih = (_Float16)f[u].y;
-            c[0][u] = f[u].x;
-            c[1][u] = f[u].y;
-            c[2][u] = f[u].x - (float)rh;
-            c[3][u] = f[u].y - (float)ih;
-            f[u] = cmul(f[u], st[u]);
-          }
-#pragma unroll
-          for (int comp = 0; comp < 4; ++comp) {
-            typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-            h2 v = {(_Float16)c[comp][0], (_Float16)c[comp][1]};
-            *reinterpret_cast<h2*>(tb + (axis * 4 + comp) * kTabH + split_row(k0 + q) + 2 * pair) = v;
-          }
+          const h2 rh = __builtin_amdgcn_cvt_pkrtz(f[0].x, f[1].x);
+          const h2 ih = __builtin_amdgcn_cvt_pkrtz(f[0].y, f[1].y);
+          const h2 rl = __builtin_amdgcn_cvt_pkrtz(f[0].x - (float)rh[0], f[1].x - (float)rh[1]);
+          const h2 il = __builtin_amdgcn_cvt_pkrtz(f[0].y - (float)ih[0], f[1].y - (float)ih[1]);
+          _Float16* dst = row + split_row(k0 + q);
+          *reinterpret_cast<h2*>(dst) = rh;
+          *reinterpret_cast<h2*>(dst + kTabH) = ih;
+          *reinterpret_cast<h2*>(dst + 2 * kTabH) = rl;
+          *reinterpret_cast<h2*>(dst + 3 * kTabH) = il;
+          f[0] = cmul(f[0], st[0]);
+          f[1] = cmul(f[1], st[1]);
         }
       }
       __syncthreads();
