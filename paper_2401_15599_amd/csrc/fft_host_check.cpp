@@ -74,8 +74,26 @@ template <class P> static int check(const char* name) {
   return ok ? 0 : 1;
 }
 
+// sincos_phase against double precision: moderate arguments, quadrant boundaries, the fallback
+static int check_sincos() {
+  double worst = 0;
+  auto probe = [&](float x) {
+    float s, c;
+    sincos_phase(x, &s, &c);
+    worst = std::max(worst, std::max(std::fabs(s - std::sin((double)x)),
+                                     std::fabs(c - std::cos((double)x))));
+  };
+  for (int i = -2000000; i <= 2000000; ++i) probe((float)i * 1.5e-4f);          // [-300, 300]
+  for (int k = -4000; k <= 4000; ++k)
+    for (int d = -3; d <= 3; ++d) probe(std::nextafter((float)(k * M_PI_4), d > 0 ? 1e9f : -1e9f) + d * 1e-6f);
+  for (int i = 0; i < 1000; ++i) probe(8000.0f + (float)i * 1.37f);             // both branches
+  const bool ok = worst < 1e-6;
+  std::printf("%-28s max abs error %.2e  %s\n", "sincos_phase", worst, ok ? "ok" : "FAIL");
+  return ok ? 0 : 1;
+}
+
 int main() {
-  int bad = 0;
+  int bad = check_sincos();
 #define TACAW_CHECK_PLAN(NAME, ...) bad += check<__VA_ARGS__>(NAME);
   TACAW_FOR_EACH_PLAN(TACAW_CHECK_PLAN)
   std::printf("%s\n", bad ? "FFT host check FAILED" : "FFT host check passed");

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       float sn, cs;
-      sincosf(sigma * vrow[l + L * j], &sn, &cs);
+      sincos_phase(sigma * vrow[l + L * j], &sn, &cs);
       tr[j] = make_float2(cs, sn);
     }
     float gacc[ADJ ? E : 1];

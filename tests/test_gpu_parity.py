@@ -238,6 +238,75 @@ def test_every_fft_schedule_matches_oracle(n, tmp_path):
     assert ran >= len(variants) // 2
 
 
+def _band_problem(seed):
+    """Two specimens of one 64 x 64 grid class with different cell widths (so different sets of
+    band-limited columns) and a probe aperture wider than the band limit (the entrance waves have
+    content in the columns outside the band)."""
+    specs = [_random_specimen(64, 64, lx, 16.0, [2.0] * 5, 40, 2, seed + j)
+             for j, lx in enumerate((16.0, 12.0))]
+    beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.12, defocus_a=30.0, cs_a=0.0,
+                           probe_xy=np.array([[5.0, 6.0], [9.5, 3.25]]))
+    ff = form_factor_table(["A", "B"])
+    # kx columns kept: |m| <= 21 of 64 for the 16 A cell, |m| <= 15 for the 12 A cell
+    out = []
+    for spec, pos, species in specs:
+        V, _ = o_pot.potentials(pos, species, ff, spec)
+        out.append((spec, V.astype(np.float32)))
+    return out, beam
+
+
+def _outside_band_columns(spec, energy_ev):
+    mp = o_ms.propagator(spec, energy_ev, spec.dz[0])
+    return np.nonzero(np.all(mp == 0, axis=0))[0]
+
+
+def test_band_limited_columns_mixed_jobs_forward():
+    jobs_np, beam = _band_problem(21)
+    jobs, outs = [], []
+    for spec, V32 in jobs_np:
+        out = torch.empty((V32.shape[0], 2, 64, 64), dtype=torch.complex64, device=DEV)
+        outs.append(out)
+        jobs.append(tw.MsJob(tw.specimen_from(spec), tw.beam_from(beam), _gpu(V32), out))
+    for mode in (tw.MODE_BATCHED, tw.MODE_PLAIN):
+        for out in outs:
+            out.fill_(float("nan"))      # stale buffer contents must never leak into the result
+        tw.tacaw_multislice(ctx(), jobs, mode=mode)
+        for (spec, V32), out in zip(jobs_np, outs):
+            ref = o_ms.exit_waves(V32.astype(np.float64), spec, beam)
+            got = out.cpu().numpy()
+            cols = _outside_band_columns(spec, beam.energy_ev)
+            assert 0 < len(cols) < 64
+            assert np.all(got[..., cols] == 0)
+            check(got, ref, 1e-4)
+
+
+def test_band_limited_columns_mixed_jobs_adjoint():
+    jobs_np, beam = _band_problem(31)
+    rng = np.random.default_rng(5)
+    stride = 2
+    jobs, gexits, gVs, refs = [], [], [], []
+    for spec, V32 in jobs_np:
+        T, S = V32.shape[:2]
+        out = torch.empty((T, 2, 64, 64), dtype=torch.complex64, device=DEV)
+        ck = torch.empty((T, 2, (S + stride - 1) // stride, 64, 64), dtype=torch.complex64,
+                         device=DEV)
+        jobs.append(tw.MsJob(tw.specimen_from(spec), tw.beam_from(beam), _gpu(V32), out, ck))
+        g = (rng.normal(size=(T, 2, 64, 64)) + 1j * rng.normal(size=(T, 2, 64, 64))) * 1e-2
+        gexits.append(_gpu(g.astype(np.complex64)))
+        gVs.append(torch.empty(V32.shape, dtype=torch.float32, device=DEV))
+        psi0 = o_ms.initial_waves(spec, beam)
+        ref = np.zeros(V32.shape)
+        for t in range(T):
+            for p in range(2):
+                ref[t] += o_adj.multislice_adjoint(psi0[p], V32[t].astype(np.float64), spec,
+                                                   beam.energy_ev, g[t, p])
+        refs.append(ref)
+    tw.tacaw_multislice(ctx(), jobs, ckpt_stride=stride)
+    tw.tacaw_multislice_adjoint(ctx(), jobs, stride, gexits, gVs)
+    for gV, ref in zip(gVs, refs):
+        check(gV.cpu().numpy(), ref, 1e-3)
+
+
 def test_batched_graph_replay_is_stable():
     w = make_workload("c1", n_snap=3)
     V, _ = o_pot.potentials(w.positions, w.species, w.ff, w)
