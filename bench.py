@@ -155,10 +155,64 @@ def adjoint_leg(tw):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    tf, ta, tax = timeit(fwd), timeit(adj), timeit(adj_xy)
+    def fwd_pot():
+        tw.tacaw_build_potentials(ctx, sp, xyz, spc, w.ff, V)
+        fwd()
+
+    tf, ta, tax, tfp = timeit(fwd), timeit(adj), timeit(adj_xy), timeit(fwd_pot)
     return dict(config="B/N-like 16x9x10 cells, 256^2, 20 slices, 128 snapshots, ckpt stride 5",
                 forward_ms=tf * 1e3, adjoint_ms=ta * 1e3, adjoint_plus_positions_ms=tax * 1e3,
-                adjoint_over_forward=ta / tf, adjoint_with_positions_over_forward=tax / tf)
+                forward_with_potentials_ms=tfp * 1e3,
+                adjoint_over_forward=ta / tf, adjoint_with_positions_over_forward=tax / tf,
+                adjoint_with_positions_over_forward_with_potentials=tax / tfp)
+
+
+def plane_wave_leg(tw):
+    """Secondary line: a homogeneous plane-wave 512^2 batch (rocksalt 40 x 40 x 20 cells,
+    0.3125 A pixels, 40 slices, 256 snapshots, trajectory seed 6001); multislice only, median of
+    5 timed calls after one warm-up call."""
+    import torch
+    from workloads.configs import make_workload
+    from workloads.trajectory import harmonic_trajectory
+    ctx = tw.context(0)
+    cfg = dict(kind="rocksalt", a=4.0, reps=(40, 40, 20), n=(512, 512), n_slices=40, dz=2.0,
+               energy=100e3, T=256, dt=5.0, n_e=256, hop=256, seed=6001, probe=False, alpha=0.0)
+    w = make_workload(cfg, generate=False, name="plane-wave-512-S40")
+    T = cfg["T"]
+    xyz = harmonic_trajectory(w.extra["structure"], T, cfg["dt"], cfg["seed"], device="cuda:0")
+    sp, bm = tw.specimen_from(w), tw.Beam(w.energy_ev)
+    V = torch.empty((T, w.n_slices, w.ny, w.nx), dtype=torch.float32, device="cuda:0")
+    tw.tacaw_build_potentials(ctx, sp, xyz, torch.from_numpy(w.species).to("cuda:0"), w.ff, V)
+    del xyz
+    ex = torch.empty((T, 1, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+    job = [tw.MsJob(sp, bm, V, ex)]
+    tw.tacaw_multislice(ctx, job, mode=tw.MODE_BATCHED)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        tw.tacaw_multislice(ctx, job, mode=tw.MODE_BATCHED)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    med = sorted(times)[len(times) // 2]
+    steps = T * w.n_slices
+    return dict(workload="plane wave, rocksalt 40x40x20 cells, 512^2, 40 slices, 256 snapshots",
+                slice_steps=steps, median_ms=med * 1e3, slice_steps_per_s=steps / med)
+
+
+def structure_factor_work(ws):
+    """Complex multiply-adds the structure-factor contraction needs per step: for every map, the
+    band-limited k points of the computed half plane (ky >= 0, the rest is the conjugate
+    reflection) times the atoms of the slice."""
+    total = 0.0
+    for w in ws:
+        kx = np.fft.fftfreq(w.nx) * w.nx / w.lx
+        ky = np.fft.fftfreq(w.ny) * w.ny / w.ly
+        kn = min(w.nx / (2 * w.lx), w.ny / (2 * w.ly))
+        kept = (ky[:, None] ** 2 + kx[None, :] ** 2) < (w.bandlimit * kn) ** 2
+        half = int(np.count_nonzero(kept[: w.ny // 2]))
+        total += w.n_snap * w.n_slices * half * (w.species.shape[0] / w.n_slices)
+    return total
 
 
 # ------------------------------------------------------------------------------------------------
@@ -314,13 +368,23 @@ def main():
     extra = {"multislice_only_slice_steps_per_s": slice_steps * args.steps / (ms_time * 1e-3)
              if ms_time else None,
              "kernel_ms_per_step": breakdown}
+    cmacs = structure_factor_work(ws) * args.steps
+    if kinds["sf"]["total_ms"]:
+        extra["structure_factor"] = {
+            "complex_mac_per_step": cmacs / args.steps,
+            "fp32_equivalent_tflops": 8.0 * cmacs / (kinds["sf"]["total_ms"] * 1e-3) / 1e12,
+            "note": "8 flops per complex multiply-add over the computed half plane; each is done "
+                    "as 3 fp16 matrix-core products of split operands"}
     if not args.no_legs:
         log("[bench] plain vs batched leg")
         extra["plain_vs_batched"] = plain_leg(tw, ctx, ws, Vs)
-        log("[bench] adjoint/forward leg")
-        del exits, Ss
+        del exits, Ss, Vs, Ps
         torch.cuda.empty_cache()
+        log("[bench] adjoint/forward leg")
         extra["adjoint"] = adjoint_leg(tw)
+        torch.cuda.empty_cache()
+        log("[bench] homogeneous plane-wave leg")
+        extra["plane_wave_512"] = plane_wave_leg(tw)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline (host cores)")

@@ -1,0 +1,62 @@
+"""Parity at the benchmark's size and launch configuration, on sampled outputs.
+
+The benchmark's 512^2 class (8 rocksalt specimens of 10..80 slices, 30 mrad probe) runs as one
+uneven batched multislice call per chunk of 8 probe positions, exactly as the benchmark launches
+it, here with 2 snapshots.  Two waves are recomputed by the FP64 oracle (the whole potential stack
+of their snapshot and the whole multislice); every other wave is checked through properties that
+hold at any size (finite values, 0.5 < sum |phi|^2 <= 1: the band limit only removes intensity).
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+import paper_2401_15599_amd as tw
+from oracle import multislice as o_ms
+from oracle import potential as o_pot
+from workloads.configs import c3_specimens, make_workload
+
+DEV = "cuda:0"
+T, POS = 2, 8
+SAMPLES = [(10, 1, 3), (30, 0, 6)]        # (slices of the specimen, snapshot, probe position)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - b).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def test_bench_configuration_sampled_waves_match_oracle():
+    cfgs = [c for c in c3_specimens() if c["n"] == (512, 512)]
+    ws = [make_workload(c, n_snap=T, name=f"c3-512-S{c['n_slices']}") for c in cfgs]
+    ctx = tw.context(0)
+    Vs, exits, jobs = [], [], []
+    for w in ws:
+        sp = tw.specimen_from(w)
+        V = torch.empty((T, w.n_slices, w.ny, w.nx), dtype=torch.float32, device=DEV)
+        tw.tacaw_build_potentials(ctx, sp, torch.from_numpy(w.positions).to(DEV),
+                                  torch.from_numpy(w.species).to(DEV), w.ff, V)
+        ex = torch.empty((T, POS, w.ny, w.nx), dtype=torch.complex64, device=DEV)
+        b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[:POS])
+        Vs.append(V)
+        exits.append(ex)
+        jobs.append(tw.MsJob(sp, b, V, ex))
+    tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
+    torch.cuda.synchronize()
+
+    for w, ex in zip(ws, exits):
+        e = ex.cpu().numpy()
+        assert np.all(np.isfinite(e.view(np.float32))), w.name
+        norm = np.sum(np.abs(e) ** 2, axis=(2, 3))
+        assert np.all(norm > 0.5) and np.all(norm <= 1.0 + 1e-4), (w.name, norm.min(), norm.max())
+
+    for S, t, p in SAMPLES:
+        j = [k for k, w in enumerate(ws) if w.n_slices == S][0]
+        w = ws[j]
+        V_ref, _ = o_pot.potentials(w.positions[t:t + 1], w.species, w.ff, w)
+        e = rel_l2(Vs[j][t].cpu().numpy(), V_ref[0])
+        assert e <= 1e-5, f"{w.name} snapshot {t}: potentials rel-L2 {e:.3e}"
+        w.probe_xy = w.probe_xy[p:p + 1]
+        phi_ref = o_ms.exit_waves(V_ref, w, w)[0, 0]
+        e = rel_l2(exits[j][t, p].cpu().numpy(), phi_ref)
+        assert e <= 1e-4, f"{w.name} snapshot {t} position {p}: exit wave rel-L2 {e:.3e}"
