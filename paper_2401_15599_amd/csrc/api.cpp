@@ -393,7 +393,8 @@ struct ClassPlan {
   std::vector<long> group_wave_prefix;   // waves in groups [0, g)
   std::vector<int4> plane_waves, probe_waves;
   int Smax = 0;
-  int kxb = 0;                     // widest band of the class's jobs
+  int kxb = 0;                     // widest band of the class's jobs (kx index)
+  int kyb = 0;                     // largest |ky index| any column of the class's jobs keeps
 };
 
 int active_prefix(const std::vector<int>& S_sorted_desc, int s) {
@@ -416,6 +417,7 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
   if (ckpt_stride < 0) fail(TACAW_E_ARG, "ckpt_stride must be >= 0");
   MsBuild b;
   b.jobs.resize(n_jobs);
+  std::vector<int> kyb_of(n_jobs, 0);
   std::map<std::pair<int, int>, int> class_of;
   for (int j = 0; j < n_jobs; ++j) {
     const tacaw_ms_job& J = jobs[j];
@@ -440,6 +442,7 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
       const std::vector<int> bl = bandlimit_table(S);
       d.nmax = upload_vec(c, bl, st, "bl");
       d.kxb = band_columns(bl);
+      kyb_of[j] = *std::max_element(bl.begin(), bl.end());
     }
     long n_ap = 1;
     if (B.kind == TACAW_PROBE) {
@@ -485,6 +488,7 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
     ClassPlan& cp = b.classes[class_of[{b.jobs[j].nx, b.jobs[j].ny}]];
     for (int t = 0; t < b.jobs[j].T; ++t) cp.groups.push_back(make_int2(j, t));
     cp.kxb = std::max(cp.kxb, b.jobs[j].kxb);
+    cp.kyb = std::max(cp.kyb, kyb_of[j]);
   }
   for (auto& cp : b.classes) {
     std::stable_sort(cp.groups.begin(), cp.groups.end(), [&](int2 a, int2 x) {
@@ -604,6 +608,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ra.ny = cp.ny;
         ra.band_in = s > 0 ? 1 : 0;   // the initial wave is not band-limited
         ra.band_out = 1;
+        ra.prune = (s > 0 && plan_prunable(cp.nx, rs.row_plan, cp.kxb)) ? 1 : 0;
         L.row(cp.nx, rs, false, ra, active_prefix(wS, s), cp.kxb);
         const int n_mid = active_prefix(wS, s + 1), n_all = active_prefix(wS, s);
         ColArgs ca{};
@@ -612,6 +617,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ca.in_buf = BUF_W;
         ca.out_buf = BUF_W;
         ca.conj_prop = 0;
+        ca.prune = plan_prunable(cp.ny, cs.col_plan, cp.kyb) ? 1 : 0;
         ca.C = cs.C;
         ca.nx = cp.nx;
         if (n_mid > 0) {
@@ -968,6 +974,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
         ca.n_waves = nw;
         ca.C = cs.C;
         ca.nx = cp.nx;
+        ca.prune = plan_prunable(cp.ny, cs.col_plan, cp.kyb) ? 1 : 0;
         // chi_{S-1} in (kx, y): G_y[conj(M P_{S-1}) G_phi] / sqrt(N)
         ca.s = S - 1;
         ca.in_buf = BUF_GEXIT;
@@ -992,6 +999,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
             ra.ny = cp.ny;
             ra.band_in = s > 0 ? 1 : 0;
             ra.band_out = 1;
+            ra.prune = (s > 0 && plan_prunable(cp.nx, rs.row_plan, cp.kxb)) ? 1 : 0;
             L.row(cp.nx, rs, false, ra, nw, cp.kxb);
             if (s < s1 - 1) {
               ColArgs fa = ca;

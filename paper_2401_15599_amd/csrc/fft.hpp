@@ -272,9 +272,23 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int N, int L, bool INV, int NS, int R, int... Rest>
+// Band pruning (PRUNE bit 0: the two middle registers E/2-1 and E/2 of the input are zero;
+// bit 1: those registers of the output are not wanted and are returned as zero).  With striped
+// storage they hold the indices N/2 - L .. N/2 + L - 1, the middle of the axis, which a band limit
+// below N/2 - L removes.  The constants let the compiler drop the work on them.
+template <int E, int PRUNE> __device__ __forceinline__ void prune_mid(float2* v, int bit) {
+  if constexpr (E >= 4) {
+    if (PRUNE & bit) {
+      v[E / 2 - 1] = make_float2(0.f, 0.f);
+      v[E / 2] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+template <int N, int L, bool INV, int NS, int PRUNE, int R, int... Rest>
 __device__ __forceinline__ void fft_rec(float2* v, const float2* tw, float2* lds, int l) {
   constexpr int E = N / L, B = E / R;
+  if constexpr (NS == 1) prune_mid<E, PRUNE>(v, 1);
   stage_compute<N, L, R, NS, INV>(v, tw);
   if constexpr (sizeof...(Rest) > 0) {
     wave_lds_sync();
@@ -285,7 +299,9 @@ __device__ __forceinline__ void fft_rec(float2* v, const float2* tw, float2* lds
     wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
-    fft_rec<N, L, INV, NS * R, Rest...>(v, (NS > 1) ? tw + B * (R - 1) : tw, lds, l);
+    fft_rec<N, L, INV, NS * R, PRUNE, Rest...>(v, (NS > 1) ? tw + B * (R - 1) : tw, lds, l);
+  } else {
+    prune_mid<E, PRUNE>(v, 2);
   }
 }
 
@@ -293,10 +309,11 @@ __device__ __forceinline__ void fft_rec(float2* v, const float2* tw, float2* lds
 // workgroup barrier.  Exchanges alternate between two LDS regions (running parity `buf`); a region
 // is rewritten only two exchanges after it was read, with a barrier in between, so one barrier per
 // exchange suffices.  With lds1 == lds0 (single buffer) a second barrier guards the rewrite.
-template <int N, int L, bool INV, int NS, int R, int... Rest>
+template <int N, int L, bool INV, int NS, int PRUNE, int R, int... Rest>
 __device__ __forceinline__ void fft_block_rec(float2* v, const float2* tw, float2* lds0,
                                               float2* lds1, int l, int& buf) {
   constexpr int E = N / L, B = E / R;
+  if constexpr (NS == 1) prune_mid<E, PRUNE>(v, 1);
   stage_compute<N, L, R, NS, INV>(v, tw);
   if constexpr (sizeof...(Rest) > 0) {
     float2* lds = buf ? lds1 : lds0;
@@ -309,23 +326,25 @@ __device__ __forceinline__ void fft_block_rec(float2* v, const float2* tw, float
     for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
     if (lds0 == lds1) __syncthreads();
     buf ^= 1;
-    fft_block_rec<N, L, INV, NS * R, Rest...>(v, (NS > 1) ? tw + B * (R - 1) : tw, lds0, lds1, l,
-                                              buf);
+    fft_block_rec<N, L, INV, NS * R, PRUNE, Rest...>(v, (NS > 1) ? tw + B * (R - 1) : tw, lds0, lds1,
+                                                     l, buf);
+  } else {
+    prune_mid<E, PRUNE>(v, 2);
   }
 }
 
 template <class P> struct FFT;
 template <int N, int L, int... Rs> struct FFT<Plan<N, L, Rs...>> {
   // unnormalised transform of one line held striped in v; lds = this line's exchange region
-  template <bool INV>
+  template <bool INV, int PRUNE = 0>
   __device__ __forceinline__ static void run(float2* v, const float2* tw, float2* lds, int l) {
-    fft_rec<N, L, INV, 1, Rs...>(v, tw, lds, l);
+    fft_rec<N, L, INV, 1, PRUNE, Rs...>(v, tw, lds, l);
   }
   // same transform when the line's lanes span several wavefronts of the workgroup
-  template <bool INV>
+  template <bool INV, int PRUNE = 0>
   __device__ __forceinline__ static void run_block(float2* v, const float2* tw, float2* lds0,
                                                    float2* lds1, int l, int& buf) {
-    fft_block_rec<N, L, INV, 1, Rs...>(v, tw, lds0, lds1, l, buf);
+    fft_block_rec<N, L, INV, 1, PRUNE, Rs...>(v, tw, lds0, lds1, l, buf);
   }
 };
 #endif

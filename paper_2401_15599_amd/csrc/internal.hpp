@@ -54,6 +54,9 @@ struct RowArgs {
   int ny;                  // rows per image (all jobs of a launch share nx, ny)
   int band_in;             // the input is zero in the columns outside the band: not read
   int band_out;            // the consumer ignores columns outside the band: not written
+  int prune;               // band_in and band_out hold and the band leaves out the two middle
+                           // registers of the plan (kx index N/2 - L .. N/2 + L - 1) in every job:
+                           // the transforms skip them (forward kernel, plans with E >= 8)
 };
 
 struct ColArgs {
@@ -72,6 +75,9 @@ struct ColArgs {
   // Inside visited tiles, a column outside its job's band is taken as zero (its output is zero
   // whatever the input, since M vanishes on the whole column).
   int tiles_lo, tiles_hi;
+  int prune;               // M vanishes for ky index N/2 - L .. N/2 + L - 1 in every column of
+                           // every job: the y transforms skip those two middle registers
+                           // (block and wave-per-column kernels, plans with E >= 8)
 };
 
 // plain batched 2-D transforms of contiguous images (potential build, position gradient)
@@ -90,6 +96,7 @@ hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hip
 hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const ColArgs& a, int grid,
                       hipStream_t st);
 int col_block_lds_bytes(int n, int plan, int C, int pingpong);
+bool plan_prunable(int n, int plan, int kb);
 // kind 2: LDS-staged tile, one line per wavefront lane group, C * 64 / LINES threads
 int col_wave_lds_bytes(int n, int plan, int C);
 int col_wave_threads(int n, int plan, int C);

@@ -13,6 +13,8 @@
 // row and one evaluation of exp(i sigma V).  Column kernel: a workgroup stages C columns x N rows
 // through LDS with coalesced row segments, each wave transforms whole columns in place in that
 // tile, and the tile is written back with coalesced stores.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace tacaw {
@@ -108,7 +110,7 @@ __device__ __forceinline__ void col_task(const ColArgs& a, int task, int tpw, in
 
 // ------------------------------------------------------------------------------------------------
 // x pass
-template <class P, bool ADJ>
+template <class P, bool ADJ, bool PR = false>
 __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES;
   __shared__ float2 lds_all[kWaves * LINES * P::LDS_LINE];
@@ -158,14 +160,16 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
       {
         const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s) + row;
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = load_if(in + l + L * j, (rmask >> j) & 1u);
+        for (int j = 0; j < E; ++j)
+          v[j] = (PR && (j == E / 2 - 1 || j == E / 2)) ? make_float2(0.f, 0.f)
+                                                         : load_if(in + l + L * j, (rmask >> j) & 1u);
       }
       if (!ADJ && a.store_ckpt) {
         GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j) ck[l + L * j] = v[j];
       }
-      FFT<P>::template run<true>(v, tw, lds, l);          // psi_s (real space)
+      FFT<P>::template run<true, PR ? 1 : 0>(v, tw, lds, l);          // psi_s (real space)
       if constexpr (!ADJ) {
         if (a.stash_slot >= 0) {
           GLOBAL_AS float2* st = gp(J.stash) + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
@@ -185,11 +189,11 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
         }
       }
       if (a.write_out) {
-        FFT<P>::template run<false>(v, tw, lds, l);
+        FFT<P>::template run<false, PR ? 2 : 0>(v, tw, lds, l);
         GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j)
-          if ((wmask >> j) & 1u) out[l + L * j] = v[j];
+          if (!(PR && (j == E / 2 - 1 || j == E / 2)) && ((wmask >> j) & 1u)) out[l + L * j] = v[j];
       }
     }
     if constexpr (ADJ) {
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
 // segments.  The next tile is prefetched into registers while the current one is transformed.
 // Twiddles live in a small LDS table (lanes sharing l read the same entry); the per-row propagator
 // factors py stay in registers across tiles of the same job.
-template <class P, bool DOFWD, bool DOINV>
+template <class P, bool DOFWD, bool DOINV, bool PR = false>
 __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, CS = P::LDS_LINE, NTW = P::NTW;
   extern __shared__ float2 lds_mem[];
@@ -331,7 +335,8 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
       py_job = wv.x;
     }
     if (task + (int)gridDim.x < n_tasks) load(task + gridDim.x);
-    if constexpr (DOFWD) FFT<P>::template run_block<false>(v, tw, reg0, reg1, l, buf);
+    if constexpr (DOFWD) FFT<P>::template run_block<false, PR ? 2 : 0>(v, tw, reg0, reg1, l, buf);
+    if constexpr (PR) prune_mid<E, 1>(v, 1);   // M is zero there (also for a raw adjoint input)
     {
       // band-limited propagator (conjugated for the adjoint; pyl is stored conjugated then)
       float2 pxs = cscale(pxm, a.scale);
@@ -345,7 +350,7 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
         v[j] = cmul(v[j], d);
       }
     }
-    if constexpr (DOINV) FFT<P>::template run_block<true>(v, tw, reg0, reg1, l, buf);
+    if constexpr (DOINV) FFT<P>::template run_block<true, PR ? 1 : 0>(v, tw, reg0, reg1, l, buf);
     CJob& J = job_at(a.jobs, wv.x);
     GLOBAL_AS float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s);
 #pragma unroll
@@ -359,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
 // prefetched into registers while the current one is transformed.  C * 64 / LINES threads.
 template <class P> constexpr int colw_max_threads() { return P::E > 8 ? 512 : 1024; }
 
-template <class P, bool DOFWD, bool DOINV>
+template <class P, bool DOFWD, bool DOINV, bool PR = false>
 __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE, NTW = P::NTW;
   extern __shared__ float2 lds_mem[];
@@ -430,7 +435,8 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
       float2 v[E];
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = reg[lds_pad(l + L * j)];
-      if constexpr (DOFWD) FFT<P>::template run<false>(v, tw, reg, l);
+      if constexpr (DOFWD) FFT<P>::template run<false, PR ? 2 : 0>(v, tw, reg, l);
+      if constexpr (PR) prune_mid<E, 1>(v, 1);   // M is zero there (also for a raw adjoint input)
       float2 pxs = cscale(pxm, a.scale);
       if (a.conj_prop) pxs.y = -pxs.y;
 #pragma unroll
@@ -441,7 +447,7 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
         if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
         v[j] = cmul(v[j], d);
       }
-      if constexpr (DOINV) FFT<P>::template run<true>(v, tw, reg, l);
+      if constexpr (DOINV) FFT<P>::template run<true, PR ? 1 : 0>(v, tw, reg, l);
 #pragma unroll
       for (int j = 0; j < E; ++j) reg[lds_pad(l + L * j)] = v[j];
     }
@@ -629,11 +635,32 @@ hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hip
   hipError_t e = hipErrorInvalidValue;
   with_plan(n, plan, [&](auto p) {
     using P = decltype(p);
-    if (adj) hipLaunchKernelGGL((k_row<P, true>), dim3(grid), dim3(kThreads), 0, st, a);
-    else hipLaunchKernelGGL((k_row<P, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    if (adj) {
+      hipLaunchKernelGGL((k_row<P, true>), dim3(grid), dim3(kThreads), 0, st, a);
+    } else {
+      bool done = false;
+      if constexpr (P::E >= 8) {
+        if (a.prune) {
+          hipLaunchKernelGGL((k_row<P, false, true>), dim3(grid), dim3(kThreads), 0, st, a);
+          done = true;
+        }
+      }
+      if (!done) hipLaunchKernelGGL((k_row<P, false>), dim3(grid), dim3(kThreads), 0, st, a);
+    }
     e = hipGetLastError();
   });
   return e;
+}
+
+// whether a plan of n points can skip its two middle registers for a band limit of kb
+// (largest kept |index|)
+bool plan_prunable(int n, int plan, int kb) {
+  bool ok = false;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    ok = P::E >= 8 && kb <= P::N / 2 - P::L - 1;
+  });
+  return ok;
 }
 
 // Dynamic LDS limits are raised once per context creation (never during graph capture).
@@ -653,6 +680,14 @@ void prepare_dynamic_lds(int max_bytes) {
         (void)hipFuncSetAttribute((const void*)k_colw<P, true, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_colw<P, true, false>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_colw<P, false, true>, (hipFuncAttribute)attr, max_bytes);
+        if constexpr (P::E >= 8) {
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, true, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, false, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, false, true, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colw<P, true, true, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colw<P, true, false, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colw<P, false, true, true>, (hipFuncAttribute)attr, max_bytes);
+        }
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, false>, (hipFuncAttribute)attr, max_bytes);
       });
@@ -702,12 +737,23 @@ hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const C
       using P = decltype(p);
       const int lds = col_wave_lds_bytes(n, plan, a.C);
       const int threads = col_wave_threads(n, plan, a.C);
-      if (dofwd && doinv)
-        hipLaunchKernelGGL((k_colw<P, true, true>), dim3(grid), dim3(threads), lds, st, a);
-      else if (dofwd)
-        hipLaunchKernelGGL((k_colw<P, true, false>), dim3(grid), dim3(threads), lds, st, a);
-      else
-        hipLaunchKernelGGL((k_colw<P, false, true>), dim3(grid), dim3(threads), lds, st, a);
+      auto go = [&](auto pr) {
+        constexpr bool PR = decltype(pr)::value;
+        if (dofwd && doinv)
+          hipLaunchKernelGGL((k_colw<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+        else if (dofwd)
+          hipLaunchKernelGGL((k_colw<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
+        else
+          hipLaunchKernelGGL((k_colw<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+      };
+      bool done = false;
+      if constexpr (P::E >= 8) {
+        if (a.prune) {
+          go(std::true_type{});
+          done = true;
+        }
+      }
+      if (!done) go(std::false_type{});
       e = hipGetLastError();
     });
     return e;
@@ -718,12 +764,23 @@ hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const C
       const int lds = ((a.pingpong ? 2 : 1) * a.C * P::LDS_LINE + P::L * P::NTW + P::N) *
                       (int)sizeof(float2);
       const int threads = a.C * P::L;
-      if (dofwd && doinv)
-        hipLaunchKernelGGL((k_colb<P, true, true>), dim3(grid), dim3(threads), lds, st, a);
-      else if (dofwd)
-        hipLaunchKernelGGL((k_colb<P, true, false>), dim3(grid), dim3(threads), lds, st, a);
-      else
-        hipLaunchKernelGGL((k_colb<P, false, true>), dim3(grid), dim3(threads), lds, st, a);
+      auto go = [&](auto pr) {
+        constexpr bool PR = decltype(pr)::value;
+        if (dofwd && doinv)
+          hipLaunchKernelGGL((k_colb<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+        else if (dofwd)
+          hipLaunchKernelGGL((k_colb<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
+        else
+          hipLaunchKernelGGL((k_colb<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+      };
+      bool done = false;
+      if constexpr (P::E >= 8) {
+        if (a.prune) {
+          go(std::true_type{});
+          done = true;
+        }
+      }
+      if (!done) go(std::false_type{});
       e = hipGetLastError();
     });
     return e;
