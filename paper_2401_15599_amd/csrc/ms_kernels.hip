@@ -86,10 +86,28 @@ __device__ __forceinline__ GLOBAL_AS float2* pick_buf(CJob& J, int code, int wav
   }
 }
 
+// The x pass streams its rows through HBM once (read once, written once, far larger than the
+// caches): its wave loads and stores carry the non-temporal hint (measured: 3.5 % faster there,
+// 7 % slower in the y pass, whose column tiles keep plain accesses).
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 load_nt(const GLOBAL_AS float2* p) {
+  const f2v x = __builtin_nontemporal_load(reinterpret_cast<const GLOBAL_AS f2v*>(p));
+  return make_float2(x.x, x.y);
+}
+__device__ __forceinline__ void store_nt(GLOBAL_AS float2* p, float2 v) {
+  const f2v x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<GLOBAL_AS f2v*>(p));
+}
+
 // *p when c holds, else zero (the load is not issued for lanes where c fails)
 __device__ __forceinline__ float2 load_if(const GLOBAL_AS float2* p, bool c) {
   float2 x = make_float2(0.f, 0.f);
   if (c) x = *p;
+  return x;
+}
+__device__ __forceinline__ float2 load_if_nt(const GLOBAL_AS float2* p, bool c) {
+  float2 x = make_float2(0.f, 0.f);
+  if (c) x = load_nt(p);
   return x;
 }
 
@@ -162,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
 #pragma unroll
         for (int j = 0; j < E; ++j)
           v[j] = (PR && (j == E / 2 - 1 || j == E / 2)) ? make_float2(0.f, 0.f)
-                                                         : load_if(in + l + L * j, (rmask >> j) & 1u);
+                                                         : load_if_nt(in + l + L * j, (rmask >> j) & 1u);
       }
       if (!ADJ && a.store_ckpt) {
         GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
@@ -193,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
         GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j)
-          if (!(PR && (j == E / 2 - 1 || j == E / 2)) && ((wmask >> j) & 1u)) out[l + L * j] = v[j];
+          if (!(PR && (j == E / 2 - 1 || j == E / 2)) && ((wmask >> j) & 1u)) store_nt(out + l + L * j, v[j]);
       }
     }
     if constexpr (ADJ) {
