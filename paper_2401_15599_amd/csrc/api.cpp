@@ -1233,8 +1233,8 @@ int tacaw_load_tuning(tacaw_ctx* ctx, const char* path) {
       if (line.find("\"n\"") == std::string::npos) continue;
       auto num = [&](const char* k) -> int {
         auto p = line.find(std::string("\"") + k + "\"");
+        if (p != std::string::npos) p = line.find(':', p);
         if (p == std::string::npos) fail(TACAW_E_ARG, std::string("tuning line lacks ") + k);
-        p = line.find(':', p);
         return std::atoi(line.c_str() + p + 1);
       };
       int n = num("n");
@@ -1361,9 +1361,14 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
         while (f && std::getline(f, line)) {
           auto p = line.find("\"n\"");
           if (p == std::string::npos) continue;
+          bool ok = true;
           auto num = [&](const char* k) {
             auto q = line.find(std::string("\"") + k + "\"");
-            q = line.find(':', q);
+            if (q != std::string::npos) q = line.find(':', q);
+            if (q == std::string::npos) {
+              ok = false;
+              return 0;
+            }
             return std::atoi(line.c_str() + q + 1);
           };
           Sched s;
@@ -1372,7 +1377,8 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
           s.C = num("C");
           s.col_kind = num("kind");
           s.pp = num("pp");
-          all[num("n")] = s;
+          const int nn = num("n");
+          if (ok) all[nn] = s;   // lines that are not complete entries are dropped
         }
       }
       all[n] = best;

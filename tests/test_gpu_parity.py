@@ -238,6 +238,39 @@ def test_every_fft_schedule_matches_oracle(n, tmp_path):
     assert ran >= len(variants) // 2
 
 
+def test_autotune_cache_round_trip(tmp_path):
+    """The autotuner's choice, written to a cache file and loaded into a fresh context, gives the
+    oracle's exit waves; the cache holds one well-formed entry per tuned size."""
+    import json
+    cache = tmp_path / "tune.jsonl"
+    cx = tw.Context(0)
+    for n in (64, 128):
+        tw.tacaw_autotune(cx, n, 8, str(cache))
+    entries = [json.loads(line) for line in cache.read_text().splitlines() if line.strip()]
+    assert sorted(e["n"] for e in entries) == [64, 128]
+    for e in entries:
+        assert 0 <= e["row"] < tw.tacaw_plan_count(e["n"]) and 0 <= e["col"] < tw.tacaw_plan_count(e["n"])
+        assert e["kind"] in (0, 1, 2) and e["C"] in (8, 16, 32, 64)
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"n": 64, "row": 0, "col": 0, "C": 16, "kind": 7, "pp": 0}\n')
+    with pytest.raises(tw.TacawError):
+        tw.tacaw_load_tuning(tw.Context(0), str(bad))
+    bad.write_text('{"n": 64, "row": 0}\n')
+    with pytest.raises(tw.TacawError):
+        tw.tacaw_load_tuning(tw.Context(0), str(bad))
+    fresh = tw.Context(0)
+    tw.tacaw_load_tuning(fresh, str(cache))
+    assert tw.tacaw_describe_schedule(fresh, 128) == tw.tacaw_describe_schedule(cx, 128)
+    spec, pos, species = _random_specimen(128, 128, 32.0, 32.0, [2.0] * 3, 60, 2, 17)
+    V, _ = o_pot.potentials(pos, species, form_factor_table(["A", "B"]), spec)
+    V32 = V.astype(np.float32)
+    beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.03, defocus_a=0.0, cs_a=0.0,
+                           probe_xy=np.array([[10.0, 12.0], [20.5, 7.25]]))
+    out = torch.empty((2, 2, 128, 128), dtype=torch.complex64, device=DEV)
+    tw.tacaw_multislice(fresh, [tw.MsJob(tw.specimen_from(spec), tw.beam_from(beam), _gpu(V32), out)])
+    check(out.cpu().numpy(), o_ms.exit_waves(V32.astype(np.float64), spec, beam), 1e-4)
+
+
 def _band_problem(seed):
     """Two specimens of one 64 x 64 grid class with different cell widths (so different sets of
     band-limited columns) and a probe aperture wider than the band limit (the entrance waves have
