@@ -753,6 +753,36 @@ int tacaw_bin_atoms(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap, 
   });
 }
 
+// pref M(k) f_Z(|k|) w(k) on the rows the position gradient visits (ky >= 0 with weight 2 for
+// ky > 0 in half-plane mode), per species; *bound = max |v| max(1, |ky|) (the H scale of the kernel)
+static std::vector<float> pos_grad_table(const tacaw_specimen& s, const double* ff, int nsp,
+                                         const std::vector<int>& nmax, bool herm, double pref,
+                                         double* bound) {
+  const int nx = s.nx, ny = s.ny, ny_h = herm ? ny / 2 : ny;
+  std::vector<float> t((size_t)nsp * ny_h * nx, 0.f);
+  double b = 0.0;
+  for (int z = 0; z < nsp; ++z) {
+    const double* f = ff + 12 * z;
+    for (int n = 0; n < ny_h; ++n) {
+      const int ns = n < ny / 2 ? n : n - ny;
+      const double ky = ns / s.ly;
+      for (int m = 0; m < nx; ++m) {
+        if (std::abs(ns) > nmax[m]) continue;
+        const int ms = m < nx / 2 ? m : m - nx;
+        const double kx = ms / s.lx, q2 = kx * kx + ky * ky;
+        const double fz = f[0] / (q2 + f[1]) + f[2] / (q2 + f[3]) + f[4] / (q2 + f[5]) +
+                          f[6] * std::exp(-f[7] * q2) + f[8] * std::exp(-f[9] * q2) +
+                          f[10] * std::exp(-f[11] * q2);
+        const double v = ((herm && n > 0) ? 2.0 : 1.0) * pref * fz;
+        t[((size_t)z * ny_h + n) * nx + m] = (float)v;
+        b = std::max(b, std::abs(v) * std::max(1.0, std::abs(ky)));
+      }
+    }
+  }
+  *bound = b;
+  return t;
+}
+
 static std::vector<float> ff_f32(const double* ff, int nsp) {
   std::vector<float> f(12 * nsp);
   for (int i = 0; i < 12 * nsp; ++i) f[i] = (float)ff[i];
@@ -847,6 +877,13 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
     int4* chunks = (int4*)workspace(ctx, "chunks", (size_t)cap * sizeof(int4) + 16);
     int* count = (int*)(chunks + cap);
     void* arec = workspace(ctx, "atom_phase", (size_t)snaps_per * n_atoms * 24);
+    const bool herm = spec->bandlimit > 0.0 && spec->bandlimit < 1.0 && spec->ny >= 128;
+    const double pref = 2.0 * kPi * kA0 * kE4pe0 / (spec->lx * spec->ly);
+    double hbound = 0.0;
+    const float* vtab = upload_vec(
+        ctx, pos_grad_table(*spec, ff, n_species, bandlimit_table(*spec), herm, pref, &hbound), st,
+        "pg_vtab");
+    float* absmax = (float*)workspace(ctx, "pg_absmax", (size_t)snaps_per * S * sizeof(float));
     for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
       const int nt = std::min(snaps_per, n_snap - t0);
       hip_check(launch_fft2_real(spec->nx, spec->ny, grad_V + (size_t)t0 * S * img, gk, nt * S, st),
@@ -873,7 +910,10 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
       a.pref = (float)(2.0 * kPi * kA0 * kE4pe0 / (spec->lx * spec->ly));
       a.nmax = nmax;
       a.arec = arec;
-      a.hermitian = (spec->bandlimit > 0.0 && spec->bandlimit < 1.0 && spec->ny >= 128) ? 1 : 0;
+      a.hermitian = herm ? 1 : 0;
+      a.vtab = vtab;
+      a.hbound = (float)hbound;
+      a.absmax_out = absmax;
       timed_launch(ctx, st, "pos_grad", 0.0, [&] {
         hip_check(launch_position_grad_chunks(a, chunks, cap, count, st), "position-gradient kernel");
       });

@@ -136,6 +136,9 @@ struct PgArgs {
   const int* nmax;
   void* arec;              // per-atom phase records of the pass (CSR order)
   int hermitian;           // visit ky >= 0 only (band limit on)
+  const float* vtab;       // [n_species][ny_h][nx] pref M(k) f_Z(|k|) w(k) (ny_h = ny/2 or ny)
+  float hbound;            // max over vtab of |v| max(1, |ky|)
+  float* absmax_out;       // [n_maps] workspace: max |Re G|, |Im G| over the visited rows
 };
 hipError_t launch_atom_phase(const float* xyz, const int* order, int t0, int nt, int n_atoms,
                              double lx, double ly, void* rec, hipStream_t st);

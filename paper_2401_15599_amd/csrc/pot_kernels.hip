@@ -429,18 +429,48 @@ hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
 
 // ---------------------------------------------------------------------------------------------
 // dL/d(x, y): one workgroup per (map, species-pure chunk of at most 64 atoms).
-// With H(k) = conj(G(k)) pref M(k) f_Z(|k|), G = DFT[dL/dV_s]:
+// With H(k) = conj(G(k)) pref M(k) f_Z(|k|) w(k), G = DFT[dL/dV_s] (w = 2 for ky > 0 rows when
+// only the ky >= 0 half is visited, else 1; the factors other than G come from vtab):
 //   T[a][m]  = sum_n ey_a(n) H(n, m),   T'[a][m] = sum_n ey_a(n) ky_n H(n, m)      (MFMA, K = ky)
 //   dx_a = 2 pi Im sum_m T[a][m] kx_m ex_a(m),   dy_a = 2 pi Im sum_m T'[a][m] ex_a(m)
 // G is Hermitian (dL/dV is real), so the summand at -k is minus the conjugate of the one at k and
 // the imaginary parts agree: with the band limit on, rows ky > 0 are visited with weight 2 and the
-// row ky = 0 with weight 1.  Four wavefronts: (atom half) x (kx half) quadrants of 32 x 32.
+// row ky = 0 with weight 1.  Both operands are split into fp16 high and low parts (as in the
+// structure factor) for v_mfma_f32_32x32x16_f16: the phases are unit numbers, and H is scaled by a
+// power of two per map (from max |G| and a host bound on the other factors) so that its split
+// parts are normal fp16 numbers; the scale is removed when T is folded with the x phases.
+// Four wavefronts: (atom half) x (kx half) quadrants of 32 x 32; ky in fills of 32.
+constexpr int kPgKy = 32;     // ky per LDS fill
+constexpr int kPgRow = 40;    // halves per table row (32 + pad: rows 80 bytes apart)
+
+// max over the visited rows (n < ny_h) of |Re G| and |Im G|, one workgroup per map
+__global__ __launch_bounds__(256) void k_map_absmax(const float2* gk, int nx, int ny, int ny_h,
+                                                    float* out) {
+  __shared__ float red[256];
+  const float2* G = gk + (size_t)blockIdx.x * nx * ny;
+  float mx = 0.f;
+  for (int i = threadIdx.x; i < ny_h * nx; i += 256) {
+    const float2 g = G[i];
+    mx = fmaxf(mx, fmaxf(fabsf(g.x), fabsf(g.y)));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chunks,
                                                       const int* n_chunks) {
-  __shared__ float2 E[kChunk][kTile + 1];     // y phases during the ky loop, then x phases
-  __shared__ float2 H[kTile][kTile + 1];
+  __shared__ __attribute__((aligned(16))) _Float16 Et[4][kChunk][kPgRow];      // y phases (split)
+  __shared__ __attribute__((aligned(16))) char hraw[8 * kTile * kPgRow * 2];   // H, ky H (split)
   __shared__ AtomPhase rec[kChunk];
   __shared__ float red[4][32][2];
+  _Float16 (*Ht)[kTile][kPgRow] = reinterpret_cast<_Float16 (*)[kTile][kPgRow]>(hraw);
+  float2 (*Ex)[kTile + 1] = reinterpret_cast<float2 (*)[kTile + 1]>(hraw);     // x phases (fold)
+  static_assert(sizeof(float2) * kChunk * (kTile + 1) <= sizeof(hraw), "x-phase table fits");
   if ((int)blockIdx.x >= *n_chunks) return;
   const int4 ch = chunks[blockIdx.x];          // (map, first CSR index, count, species)
   const int map = ch.x, c0 = ch.y, na = ch.z, z = ch.w;
@@ -453,103 +483,177 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
     if (tid < na) r = R[c0 + tid];
     rec[tid] = r;
   }
-  float f[12];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) f[i] = a.ff[12 * z + i];
   const float2* G = a.gk + (size_t)map * a.nx * a.ny;
-  const int TW = min(kTile, a.nx), TH = min(kTile, a.ny);
   const int herm = a.hermitian;
+  const int ny_h = herm ? a.ny / 2 : a.ny;
+  const float* vt = a.vtab + (size_t)z * ny_h * a.nx;
+  const int TW = min(kTile, a.nx);
   const int tx_n = a.nx / TW;
-  const int ty_n = herm ? (a.ny / 2 + TH - 1) / TH : a.ny / TH;
+  // power-of-two scale of H for this map
+  float hs = 1.f;
+  {
+    const float b = a.absmax_out[map] * a.hbound;
+    if (b > 0.f && b < 3.0e38f) {
+      int e;
+      (void)frexpf(b, &e);                      // b <= 2^e
+      hs = ldexpf(1.f, 14 - e);
+    }
+  }
+  const float inv_hs = 1.f / hs;
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) { sx[r] = 0.f; sy[r] = 0.f; }
 
-  // fill E[atom][k] for k < lim with exp(-2 pi i idx(k0 + k) U), in blocks of 8 from one exact factor
-  auto fill_phases = [&](int axis, int k0, int lim, int nn) {
+  for (int tx = 0; tx < tx_n; ++tx) {
+    const int m0 = tx * TW;
+    v16f cr = {0}, ci = {0}, tr = {0}, ti = {0};
+    int used = 0;
+    for (int n0 = 0; n0 < ny_h; n0 += kPgKy) {
+      const int kh = min(kPgKy, ny_h - n0);
+      int minabs_n = 1 << 30;
+      for (int n = n0; n < n0 + kh; ++n) {
+        const int ns = n < a.ny / 2 ? n : n - a.ny;
+        minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
+      }
+      int any = 0;
+      for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
+      if (!__syncthreads_or(any)) continue;     // also: the previous fill's readers are done
+      used = 1;
+      // H and ky H for (kx = m0 + c, ky rows n0 + 8 kb + q): 8 consecutive ky per thread
+      {
+        const int c = tid & 63, kb = tid >> 6;
+        const int m = m0 + c;
+        _Float16 hv[8][8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int n = n0 + 8 * kb + q;
+          float2 h = make_float2(0.f, 0.f);
+          float ky = 0.f;
+          if (c < TW && n < n0 + kh) {
+            const int ns = n < a.ny / 2 ? n : n - a.ny;
+            ky = (float)ns / (float)a.ly;
+            const float v = vt[(size_t)n * a.nx + m] * hs;
+            const float2 g = G[(size_t)n * a.nx + m];
+            h = make_float2(g.x * v, -g.y * v);
+          }
+          const float2 hp = make_float2(ky * h.x, ky * h.y);
+          const float comps[4] = {h.x, h.y, hp.x, hp.y};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const _Float16 hi = (_Float16)comps[u];
+            hv[2 * u][q] = hi;                                   // high parts: 0 Re H, 2 Im H, ...
+            hv[2 * u + 1][q] = (_Float16)(comps[u] - (float)hi); // low parts
+          }
+        }
+        // table order: 0 Re H hi, 1 Im H hi, 2 Re H lo, 3 Im H lo, 4..7 the same for ky H
+        const int order[8] = {0, 2, 1, 3, 4, 6, 5, 7};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          v8h pk;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) pk[q] = hv[u][q];
+          *reinterpret_cast<v8h*>(&Ht[order[u]][c][8 * kb]) = pk;
+        }
+      }
+      // y phases of the 64 atoms at ky rows n0 + 8 kb .. + 7 (exact start, unit steps)
+      {
+        const int at = tid & 63, kb = tid >> 6;
+        const int n = n0 + 8 * kb;
+        const int sidx = n < a.ny / 2 ? n : n - a.ny;
+        float2 f = make_float2(0.f, 0.f), st = make_float2(0.f, 0.f);
+        if (at < na && 8 * kb < kh) {
+          f = phase_factor(sidx, rec[at].uy);
+          st = rec[at].sy;
+        }
+        v8h rh, ih, rl, il;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const _Float16 a_hi = (_Float16)f.x, b_hi = (_Float16)f.y;
+          rh[q] = a_hi;
+          ih[q] = b_hi;
+          rl[q] = (_Float16)(f.x - (float)a_hi);
+          il[q] = (_Float16)(f.y - (float)b_hi);
+          f = cmul(f, st);
+        }
+        *reinterpret_cast<v8h*>(&Et[0][at][8 * kb]) = rh;
+        *reinterpret_cast<v8h*>(&Et[1][at][8 * kb]) = ih;
+        *reinterpret_cast<v8h*>(&Et[2][at][8 * kb]) = rl;
+        *reinterpret_cast<v8h*>(&Et[3][at][8 * kb]) = il;
+      }
+      __syncthreads();
+      const int ar = 32 * wa + li, hc = 32 * wk + li;
+#pragma unroll
+      for (int b = 0; b < kPgKy / 16; ++b) {
+        const int kb = 16 * b + 8 * lk;
+        const v8h erh = *reinterpret_cast<const v8h*>(&Et[0][ar][kb]);
+        const v8h eih = *reinterpret_cast<const v8h*>(&Et[1][ar][kb]);
+        const v8h erl = *reinterpret_cast<const v8h*>(&Et[2][ar][kb]);
+        const v8h eil = *reinterpret_cast<const v8h*>(&Et[3][ar][kb]);
+        const v8h neih = -eih, neil = -eil;
+        const v8h hrh = *reinterpret_cast<const v8h*>(&Ht[0][hc][kb]);
+        const v8h hih = *reinterpret_cast<const v8h*>(&Ht[1][hc][kb]);
+        const v8h hrl = *reinterpret_cast<const v8h*>(&Ht[2][hc][kb]);
+        const v8h hil = *reinterpret_cast<const v8h*>(&Ht[3][hc][kb]);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, hrh, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, hih, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, hrl, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, hil, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(erl, hrh, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(erl, hih, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(neih, hih, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(eih, hrh, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(neih, hil, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(eih, hrl, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(neil, hih, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(eil, hrh, ci, 0, 0, 0);
+        const v8h prh = *reinterpret_cast<const v8h*>(&Ht[4][hc][kb]);
+        const v8h pih = *reinterpret_cast<const v8h*>(&Ht[5][hc][kb]);
+        const v8h prl = *reinterpret_cast<const v8h*>(&Ht[6][hc][kb]);
+        const v8h pil = *reinterpret_cast<const v8h*>(&Ht[7][hc][kb]);
+        tr = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, prh, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, pih, ti, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, prl, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x16_f16(erh, pil, ti, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_32x32x16_f16(erl, prh, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x16_f16(erl, pih, ti, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_32x32x16_f16(neih, pih, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x16_f16(eih, prh, ti, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_32x32x16_f16(neih, pil, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x16_f16(eih, prl, ti, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_32x32x16_f16(neil, pih, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_32x32x16_f16(eil, prh, ti, 0, 0, 0);
+      }
+    }
+    if (!used) continue;
+    // fold with the x phases of this kx tile (table aliases H: wait for the last MFMA readers)
+    __syncthreads();
     for (int i = tid; i < kChunk * (kTile / 8); i += 256) {
       const int at = i / (kTile / 8), kb = (i % (kTile / 8)) * 8;
-      float2* dst = &E[at][kb];
-      if (at >= na || kb >= lim) {
+      float2* dst = &Ex[at][kb];
+      if (at >= na || kb >= TW) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) dst[q] = make_float2(0.f, 0.f);
         continue;
       }
-      const int idx = k0 + kb, sidx = idx < nn / 2 ? idx : idx - nn;
-      float2 ph = phase_factor(sidx, axis == 0 ? rec[at].ux : rec[at].uy);
-      const float2 st = axis == 0 ? rec[at].sx : rec[at].sy;
+      const int idx = m0 + kb, sidx = idx < a.nx / 2 ? idx : idx - a.nx;
+      float2 ph = phase_factor(sidx, rec[at].ux);
+      const float2 st = rec[at].sx;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         dst[q] = ph;
         ph = cmul(ph, st);
       }
     }
-  };
-
-  for (int tx = 0; tx < tx_n; ++tx) {
-    const int m0 = tx * TW;
-    v16f cr = {0}, ci = {0}, tr = {0}, ti = {0};
-    int used = 0;
-    for (int ty = 0; ty < ty_n; ++ty) {
-      const int n0 = ty * TH;
-      int minabs_n = 1 << 30;
-      for (int n = n0; n < n0 + TH; ++n) {
-        int ns = n < a.ny / 2 ? n : n - a.ny;
-        minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
-      }
-      int any = 0;
-      for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
-      if (!__syncthreads_or(any)) continue;
-      used = 1;
-      for (int i = tid; i < kTile * kTile; i += 256) {
-        const int r = i / kTile, c = i % kTile;
-        float2 h = make_float2(0.f, 0.f);
-        if (r < TH && c < TW) {
-          const int n = n0 + r, m = m0 + c;
-          const int ns = n < a.ny / 2 ? n : n - a.ny, ms = m < a.nx / 2 ? m : m - a.nx;
-          if ((ns < 0 ? -ns : ns) <= a.nmax[m] && (!herm || n < a.ny / 2)) {
-            const float ky = (float)ns / (float)a.ly, kx = (float)ms / (float)a.lx;
-            const float wgt = (herm && n > 0) ? 2.f : 1.f;
-            const float v = wgt * a.pref * form_factor(f, kx * kx + ky * ky);
-            const float2 g = G[(size_t)n * a.nx + m];
-            h = make_float2(g.x * v, -g.y * v);
-          }
-        }
-        H[r][c] = h;
-      }
-      fill_phases(1, n0, TH, a.ny);
-      __syncthreads();
-      for (int p = 0; p < kTile / 2; ++p) {
-        const int k = 2 * p + lk;
-        const int n = n0 + k, ns = n < a.ny / 2 ? n : n - a.ny;
-        const float ky = (float)ns / (float)a.ly;
-        const float2 av = E[32 * wa + li][k];
-        const float2 bv = H[k][32 * wk + li];
-        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.y, ci, 0, 0, 0);
-        tr = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x * ky, bv.x, tr, 0, 0, 0);
-        ti = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x * ky, bv.y, ti, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bv.y, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.x, ci, 0, 0, 0);
-        tr = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y * ky, bv.y, tr, 0, 0, 0);
-        ti = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y * ky, bv.x, ti, 0, 0, 0);
-      }
-      __syncthreads();
-    }
-    if (!used) continue;
-    // fold with the x phases of this kx tile
-    fill_phases(0, m0, TW, a.nx);
     __syncthreads();
     const int col = 32 * wk + li, m = m0 + col, ms = m < a.nx / 2 ? m : m - a.nx;
     const float kx = (float)ms / (float)a.lx;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = 32 * wa + (r & 3) + 4 * lk + 8 * (r >> 2);
-      const float2 e = E[row][col];
-      sx[r] += kx * (cr[r] * e.y + ci[r] * e.x);
-      sy[r] += tr[r] * e.y + ti[r] * e.x;
+      const float2 e = Ex[row][col];
+      sx[r] += inv_hs * kx * (cr[r] * e.y + ci[r] * e.x);
+      sy[r] += inv_hs * (tr[r] * e.y + ti[r] * e.x);
     }
-    __syncthreads();
   }
   // sum over the 32 columns held by the lanes li of each half-wave
 #pragma unroll
@@ -632,6 +736,11 @@ hipError_t launch_chunk_list(const int* offsets, int t0, int nt, int S, int nsp,
 hipError_t launch_position_grad_chunks(const PgArgs& a, const int4* chunks, int cap,
                                        const int* count, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
+  const int ny_h = a.hermitian ? a.ny / 2 : a.ny;
+  hipLaunchKernelGGL(k_map_absmax, dim3(a.n_maps), dim3(256), 0, st, a.gk, a.nx, a.ny, ny_h,
+                     a.absmax_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_position_grad, dim3(cap), dim3(256), 0, st, a, chunks, count);
   return hipGetLastError();
 }
