@@ -318,9 +318,9 @@ template <class T> T* upload_vec(tacaw_ctx* c, const std::vector<T>& v, hipStrea
 
 void validate_spec(const tacaw_specimen* s) {
   if (!s) fail(TACAW_E_ARG, "null specimen");
-  if (!pow2_in(s->nx, 16, 1024) || !pow2_in(s->ny, 16, 1024))
-    fail(TACAW_E_SIZE, "grid must be powers of two in [16, 1024], got " + std::to_string(s->nx) +
-                           "x" + std::to_string(s->ny));
+  if (!grid_size_ok(s->nx) || !grid_size_ok(s->ny))
+    fail(TACAW_E_SIZE, "grid must be a power of two in [16, 1024], 560 or 1000 per axis, got " +
+                           std::to_string(s->nx) + "x" + std::to_string(s->ny));
   if (!(s->lx > 0) || !(s->ly > 0)) fail(TACAW_E_ARG, "cell lengths must be positive");
   if (s->n_slices < 1 || !s->dz) fail(TACAW_E_ARG, "need n_slices >= 1 and dz");
   for (int i = 0; i < s->n_slices; ++i)
@@ -342,9 +342,11 @@ Sched schedule_for(tacaw_ctx* c, int n) {
   if (it != c->sched.end()) return it->second;
   // built-in choices: tacaw_autotune on an MI355X over 1 GiB batches of waves per grid size
   // {n, row plan, column plan, C, kind, pp}
+  // (560 and 1000: the staged y pass, the one kind their plans' LDS last stage leaves open to
+  // every column count)
   static const int table[][6] = {{16, 1, 1, 16, 1, 1},  {32, 0, 0, 16, 2, 0},  {64, 0, 0, 64, 1, 0},
                                  {128, 0, 0, 32, 1, 0}, {256, 0, 1, 32, 2, 0}, {512, 0, 0, 16, 1, 1},
-                                 {1024, 0, 0, 8, 2, 0}};
+                                 {1024, 0, 0, 8, 2, 0}, {560, 0, 0, 16, 0, 0},  {1000, 0, 0, 8, 0, 0}};
   Sched s;
   s.row_plan = 0;
   s.col_plan = 0;
@@ -362,23 +364,32 @@ Sched schedule_for(tacaw_ctx* c, int n) {
   return s;
 }
 
-// fit the column tile to the image width, the workgroup size and the LDS budget
+// fit the column tile to the image width (C divides nx), the workgroup size and the LDS budget
+// (dynamic tile plus the plan's static root table); a kind the plan cannot run falls back to 0
 Sched fit_cols(tacaw_ctx* c, int ny, Sched s, int nx) {
   s.C = std::min(s.C, nx);
+  while (s.C > 1 && nx % s.C != 0) s.C /= 2;
+  if (!plan_kind_ok(ny, s.col_plan, s.col_kind)) s.col_kind = 0;
+  const int budget = c->max_lds - plan_static_lds(ny, s.col_plan);
   if (s.col_kind == 1) {
     const int L = plan_lanes(ny, s.col_plan);
     while (s.C > 1 && s.C * L > 1024) s.C /= 2;
-    if (s.pp && col_block_lds_bytes(ny, s.col_plan, s.C, 1) > c->max_lds) s.pp = 0;
-    while (s.C > 1 && col_block_lds_bytes(ny, s.col_plan, s.C, s.pp) > c->max_lds) s.C /= 2;
+    if (s.pp && col_block_lds_bytes(ny, s.col_plan, s.C, 1) > budget) s.pp = 0;
+    while (s.C > 1 && col_block_lds_bytes(ny, s.col_plan, s.C, s.pp) > budget) s.C /= 2;
   } else if (s.col_kind == 2) {
+    const int C0 = s.C;
     while (s.C > 1 && (col_wave_threads(ny, s.col_plan, s.C) > 1024 ||
-                       col_wave_lds_bytes(ny, s.col_plan, s.C) > c->max_lds))
+                       col_wave_lds_bytes(ny, s.col_plan, s.C) > budget))
       s.C /= 2;
     if (col_wave_threads(ny, s.col_plan, s.C) > 1024 ||
-        col_wave_lds_bytes(ny, s.col_plan, s.C) > c->max_lds)
-      fail(TACAW_E_ARG, "wave-per-column y pass: no column count fits grid " + std::to_string(ny));
+        col_wave_lds_bytes(ny, s.col_plan, s.C) > budget) {
+      // no column count both divides nx and gives whole lines per wavefront: staged kind
+      s.col_kind = 0;
+      s.C = C0;
+      while (s.C > 1 && col_lds_bytes(ny, s.col_plan, s.C) > budget) s.C /= 2;
+    }
   } else {
-    while (s.C > 1 && col_lds_bytes(ny, s.col_plan, s.C) > c->max_lds) s.C /= 2;
+    while (s.C > 1 && col_lds_bytes(ny, s.col_plan, s.C) > budget) s.C /= 2;
   }
   return s;
 }
@@ -1085,9 +1096,13 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
 // ------------------------------------------------------------------------------------------------
 static void validate_spectrum(int nx, int ny, int n_snap, int n_pos, const tacaw_c64* exit,
                               int n_e, int hop) {
-  if (!pow2_in(nx, 16, 1024) || !pow2_in(ny, 16, 1024)) fail(TACAW_E_SIZE, "grid size");
+  if (!grid_size_ok(nx) || !grid_size_ok(ny)) fail(TACAW_E_SIZE, "grid size");
   if (n_snap < 1 || n_pos < 1 || !exit) fail(TACAW_E_ARG, "bad exit stack");
   if (!pow2_in(n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
+  // the time-line kernels take whole tiles of consecutive q
+  if (((long)nx * ny) % spectrum_q_tile(n_e) != 0)
+    fail(TACAW_E_SIZE, "nx * ny must be a multiple of " + std::to_string(spectrum_q_tile(n_e)) +
+                           " for n_e = " + std::to_string(n_e));
   if (hop < 1) fail(TACAW_E_ARG, "hop must be >= 1");
   if (n_e > n_snap) fail(TACAW_E_ARG, "segment longer than the trajectory");
 }
@@ -1254,10 +1269,10 @@ static std::string sched_line(int n, const Sched& s) {
   return o.str();
 }
 
-int tacaw_plan_count(int32_t n) { return pow2_in(n, 16, 1024) ? n_plans(n) : 0; }
+int tacaw_plan_count(int32_t n) { return grid_size_ok(n) ? n_plans(n) : 0; }
 
 const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n) {
-  if (!ctx || !pow2_in(n, 16, 1024)) return "";
+  if (!ctx || !grid_size_ok(n)) return "";
   ctx->desc = sched_line(n, schedule_for(ctx, n));
   return ctx->desc.c_str();
 }
@@ -1284,9 +1299,9 @@ int tacaw_load_tuning(tacaw_ctx* ctx, const char* path) {
       s.C = num("C");
       s.col_kind = num("kind");
       s.pp = num("pp");
-      if (!pow2_in(n, 16, 1024) || s.row_plan < 0 || s.row_plan >= n_plans(n) || s.col_plan < 0 ||
-          s.col_plan >= n_plans(n) || !pow2_in(s.C, 1, 64) || s.col_kind < 0 || s.col_kind > 2 ||
-          s.pp < 0 || s.pp > 1)
+      if (!grid_size_ok(n) || s.row_plan < 0 || s.row_plan >= n_plans(n) || s.col_plan < 0 ||
+          s.col_plan >= n_plans(n) || !pow2_in(s.C, 1, 64) || n % s.C != 0 || s.col_kind < 0 ||
+          s.col_kind > 2 || s.pp < 0 || s.pp > 1 || !plan_kind_ok(n, s.col_plan, s.col_kind))
         fail(TACAW_E_ARG, "malformed tuning entry");
       ctx->sched[n] = s;
     }
@@ -1297,7 +1312,7 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
                    void* stream) {
   return guarded([&] {
     use_device(ctx);
-    if (!pow2_in(n, 16, 1024)) fail(TACAW_E_SIZE, "grid must be a power of two in [16, 1024]");
+    if (!grid_size_ok(n)) fail(TACAW_E_SIZE, "grid must be a power of two in [16, 1024], 560 or 1000");
     if (n_waves < 1) fail(TACAW_E_ARG, "n_waves must be >= 1");
     hipStream_t st = (hipStream_t)stream;
     const size_t img = (size_t)n * n;
@@ -1355,12 +1370,13 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
       for (int kind = 0; kind < 3; ++kind)
       for (int pp = 0; pp < (kind == 1 ? 2 : 1); ++pp)
       for (int C = 8; C <= 64; C *= 2) {
-        if (C > n) continue;
-        if (kind == 0 && col_lds_bytes(n, cpn, C) > ctx->max_lds) continue;
+        if (C > n || n % C != 0 || !plan_kind_ok(n, cpn, kind)) continue;
+        const int budget = ctx->max_lds - plan_static_lds(n, cpn);
+        if (kind == 0 && col_lds_bytes(n, cpn, C) > budget) continue;
         if (kind == 1 && (C * plan_lanes(n, cpn) > 1024 ||
-                          col_block_lds_bytes(n, cpn, C, pp) > ctx->max_lds)) continue;
+                          col_block_lds_bytes(n, cpn, C, pp) > budget)) continue;
         if (kind == 2 && (col_wave_threads(n, cpn, C) > 1024 ||
-                          col_wave_lds_bytes(n, cpn, C) > ctx->max_lds)) continue;
+                          col_wave_lds_bytes(n, cpn, C) > budget)) continue;
         Sched sc = best;
         sc.col_plan = cpn;
         sc.C = C;

@@ -11,6 +11,14 @@
 // striped again, so only the m-1 intermediate stages exchange data through LDS.  The lines of a
 // wave never share LDS, so no workgroup barrier is needed inside a transform.
 //
+// Lengths with odd factors (560 = 4 x 5 x 4 x 7 on 28 lanes, 1000 = 4 x 5 x 5 x 10 on 50 lanes)
+// use the same scheme with one extension: the last radix need not divide E.  The last stage of a Stockham plan reads and writes
+// the same positions b + (N/R) r, so it can run in place in the line's LDS region, each lane taking
+// butterflies b = l, l + L, ... in rounds.  All twiddles of such a plan come from a table of the
+// N-th roots of unity that the workgroup keeps in LDS (exp(-2 pi i m / N) at m; a stage of span NS
+// and radix R reads entry (b mod NS) r N / (NS R)).  L need not divide 64 either (the lanes past
+// the last whole line of a wavefront stay idle).
+//
 // The per-lane pieces (butterflies, output positions, twiddle generation) are __host__ __device__
 // so that a CPU emulation of the lanes can check the index algebra against a plain DFT.
 #pragma once
@@ -131,6 +139,160 @@ template <bool INV> TACAW_HD void dft16(float2* x) {
 template <> TACAW_HD void dft<16, false>(float2* x) { dft16<false>(x); }
 template <> TACAW_HD void dft<16, true>(float2* x) { dft16<true>(x); }
 
+// cos and sin of 2 pi m / n in double precision at compile time: reduction to the nearest quarter
+// turn with an exact integer numerator, then Taylor series on |r| <= pi/4
+constexpr double ct_sincos2pi(long m, long n, bool want_sin) {
+  m %= n;
+  if (m < 0) m += n;
+  const long q = (4 * m + n / 2) / n;                        // nearest quarter turn
+  const double r = (double)(4 * m - q * n) * 3.14159265358979323846 / (2.0 * (double)n);
+  double ts = r, tc = 1.0, es = r, ec = 1.0;
+  for (int k = 1; k < 12; ++k) {
+    es *= -r * r / (double)((2 * k) * (2 * k + 1));
+    ec *= -r * r / (double)((2 * k - 1) * (2 * k));
+    ts += es;
+    tc += ec;
+  }
+  switch (q & 3) {
+    case 0: return want_sin ? ts : tc;
+    case 1: return want_sin ? tc : -ts;
+    case 2: return want_sin ? -ts : -tc;
+    default: return want_sin ? -tc : ts;
+  }
+}
+
+// cos and sin of 2 pi j / N, j < N, as float constants
+template <int N> struct RootTable {
+  float c[N], s[N];
+  constexpr RootTable() : c(), s() {
+    for (int j = 0; j < N; ++j) {
+      c[j] = (float)ct_sincos2pi(j, N, false);
+      s[j] = (float)ct_sincos2pi(j, N, true);
+    }
+  }
+};
+template <int N> inline constexpr RootTable<N> kRoots{};
+
+// exp(-+2 pi i j / N) (forward / inverse), j reduced mod N at compile time
+template <int N, bool INV> TACAW_HD float2 root(int j) {
+  const int k = ((j % N) + N) % N;
+  return INV ? make_float2(kRoots<N>.c[k], kRoots<N>.s[k]) : make_float2(kRoots<N>.c[k], -kRoots<N>.s[k]);
+}
+
+// odd prime R: inputs paired as a_m = x_m + x_{R-m}, b_m = x_m - x_{R-m}; then
+// X_k = x_0 + sum_m a_m cos(2 pi m k / R) -+ i sum_m b_m sin(2 pi m k / R) and X_{R-k} with the
+// other sign (upper signs forward)
+template <int R, bool INV> TACAW_HD void dft_prime(float2* x) {
+  constexpr int H = (R - 1) / 2;
+  float2 a[H], b[H];
+  float2 sum = x[0];
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    a[m - 1] = cadd(x[m], x[R - m]);
+    b[m - 1] = csub(x[m], x[R - m]);
+    sum = cadd(sum, a[m - 1]);
+  }
+  float2 y[R];
+  y[0] = sum;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    float2 re = x[0], im = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      const int j = (m * k) % R;
+      const float c = kRoots<R>.c[j], sn = kRoots<R>.s[j];
+      re = make_float2(fmaf(a[m - 1].x, c, re.x), fmaf(a[m - 1].y, c, re.y));
+      im = make_float2(fmaf(b[m - 1].x, sn, im.x), fmaf(b[m - 1].y, sn, im.y));
+    }
+    const float2 t = mul_mi<INV>(im);     // -i im (forward) or +i im (inverse)
+    y[k] = cadd(re, t);
+    y[R - k] = csub(re, t);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) x[k] = y[k];
+}
+
+template <> TACAW_HD void dft<3, false>(float2* x) { dft_prime<3, false>(x); }
+template <> TACAW_HD void dft<3, true>(float2* x) { dft_prime<3, true>(x); }
+template <> TACAW_HD void dft<5, false>(float2* x) { dft_prime<5, false>(x); }
+template <> TACAW_HD void dft<5, true>(float2* x) { dft_prime<5, true>(x); }
+template <> TACAW_HD void dft<7, false>(float2* x) { dft_prime<7, false>(x); }
+template <> TACAW_HD void dft<7, true>(float2* x) { dft_prime<7, true>(x); }
+
+// modular inverse of a mod m (gcd 1) at compile time
+constexpr int ct_inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+// N = R1 R2 with gcd(R1, R2) = 1 (Good and Thomas): n = (R2 n1 + R1 n2) mod N and k the number
+// with k = k1 mod R1, k = k2 mod R2; then X_k = sum_n1 W_R1^(n1 k1) sum_n2 W_R2^(n2 k2) x_n, with
+// no twiddle factors between the two sets of short transforms
+template <int R1, int R2, bool INV> TACAW_HD void dft_pfa(float2* x) {
+  constexpr int N = R1 * R2;
+  constexpr int E1 = R2 * ct_inv_mod(R2 % R1, R1), E2 = R1 * ct_inv_mod(R1 % R2, R2);
+  float2 y[N];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    float2 t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = x[(R2 * n1 + R1 * n2) % N];
+    dft<R2, INV>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[n1 * R2 + k2] = t[k2];
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    float2 t[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) t[n1] = y[n1 * R2 + k2];
+    dft<R1, INV>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) x[(k1 * E1 + k2 * E2) % N] = t[k1];
+  }
+}
+
+// N = R1 R2 (Cooley and Tukey): n = n1 + R1 n2, k = R2 k1 + k2;
+// X_k = sum_n1 W_R1^(n1 k1) W_N^(n1 k2) sum_n2 W_R2^(n2 k2) x_n
+template <int R1, int R2, bool INV> TACAW_HD void dft_ct(float2* x) {
+  constexpr int N = R1 * R2;
+  float2 y[N];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    float2 t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = x[n1 + R1 * n2];
+    dft<R2, INV>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[n1 * R2 + k2] = (n1 * k2 == 0) ? t[k2] : cmul(t[k2], root<N, INV>(n1 * k2));
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    float2 t[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) t[n1] = y[n1 * R2 + k2];
+    dft<R1, INV>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) x[R2 * k1 + k2] = t[k1];
+  }
+}
+
+template <> TACAW_HD void dft<10, false>(float2* x) { dft_pfa<2, 5, false>(x); }
+template <> TACAW_HD void dft<10, true>(float2* x) { dft_pfa<2, 5, true>(x); }
+template <> TACAW_HD void dft<14, false>(float2* x) { dft_pfa<2, 7, false>(x); }
+template <> TACAW_HD void dft<14, true>(float2* x) { dft_pfa<2, 7, true>(x); }
+template <> TACAW_HD void dft<20, false>(float2* x) { dft_pfa<4, 5, false>(x); }
+template <> TACAW_HD void dft<20, true>(float2* x) { dft_pfa<4, 5, true>(x); }
+template <> TACAW_HD void dft<28, false>(float2* x) { dft_pfa<4, 7, false>(x); }
+template <> TACAW_HD void dft<28, true>(float2* x) { dft_pfa<4, 7, true>(x); }
+template <> TACAW_HD void dft<25, false>(float2* x) { dft_ct<5, 5, false>(x); }
+template <> TACAW_HD void dft<25, true>(float2* x) { dft_ct<5, 5, true>(x); }
+template <> TACAW_HD void dft<35, false>(float2* x) { dft_pfa<5, 7, false>(x); }
+template <> TACAW_HD void dft<35, true>(float2* x) { dft_pfa<5, 7, true>(x); }
+template <> TACAW_HD void dft<40, false>(float2* x) { dft_pfa<8, 5, false>(x); }
+template <> TACAW_HD void dft<40, true>(float2* x) { dft_pfa<8, 5, true>(x); }
+
 // sin(pi x), cos(pi x) for an exactly representable rational x (twiddle generation)
 TACAW_HD void sincospi_f(float x, float* s, float* c) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -183,16 +345,37 @@ template <int N_, int L_, int... Rs> struct Plan {
   static constexpr int N = N_;
   static constexpr int L = L_;
   static constexpr int E = N_ / L_;
-  static constexpr int LINES = 64 / L_;       // lines per wavefront
-  static_assert(L_ >= 1 && L_ <= 64 && (64 % L_) == 0, "lanes per line must divide 64");
+  static constexpr int LINES = 64 / L_;       // whole lines per wavefront
+  static constexpr bool FULL = (64 % L_) == 0;   // the lines fill the wavefront
+  static constexpr bool POW2 = (N_ & (N_ - 1)) == 0;
+  static_assert(L_ >= 1 && L_ <= 64 && (N_ % L_) == 0, "lanes per line must divide N, at most 64");
   static_assert((1 * ... * Rs) == N_, "radices must multiply to N");
-  static_assert((((E % Rs) == 0) && ...), "every radix must divide E");
-  static constexpr int twiddle_count() {
-    int ns = 1, total = 0;
+  static constexpr int radix(int k) {
     int rs[] = {Rs...};
-    for (int k = 0; k < (int)sizeof...(Rs); ++k) {
-      if (ns > 1) total += (E / rs[k]) * (rs[k] - 1);
-      ns *= rs[k];
+    return rs[k];
+  }
+  static constexpr int NR = (int)sizeof...(Rs);
+  // the last radix may leave a remainder in E (in-place LDS stage); all others divide E
+  static constexpr bool LDS_LAST = (E % radix(NR - 1)) != 0;
+  static constexpr bool radices_ok() {
+    for (int k = 0; k + 1 < NR; ++k)
+      if (E % radix(k) != 0) return false;
+    return !LDS_LAST || NR >= 2;
+  }
+  static_assert(radices_ok(), "every radix but the last must divide E");
+  // lengths that are not powers of two take every twiddle from the LDS root table
+  static constexpr int TABN = POW2 ? 0 : N_;
+  TACAW_HD static int pad(int p) {
+    if constexpr (POW2) return p + (p >> 3);
+    else return p;
+  }
+  static_assert(!LDS_LAST || !POW2, "an LDS last stage needs the root table");
+  static constexpr int twiddle_count() {
+    if (!POW2) return 0;
+    int ns = 1, total = 0;
+    for (int k = 0; k < NR; ++k) {
+      if (ns > 1 && E % radix(k) == 0) total += (E / radix(k)) * (radix(k) - 1);
+      ns *= radix(k);
     }
     return total;
   }
@@ -204,19 +387,40 @@ template <int N_, int L_, int... Rs> struct Plan {
 
 TACAW_HD int lds_pad(int p) { return p + (p >> 3); }
 
-// butterflies of one stage for one lane; v holds E values striped, tw the stage's twiddles
-template <int N, int L, int R, int NS, bool INV>
-TACAW_HD void stage_compute(float2* v, const float2* tw) {
+// LDS position of element p of an N-point line: one pad word per 8 for powers of two (their
+// strides are multiples of 8, so the padded addresses stay affine in the register index); no
+// padding otherwise (lane counts such as 28 or 50 would make every register need its own address)
+template <int N> TACAW_HD int pad_of(int p) {
+  if constexpr ((N & (N - 1)) == 0) return lds_pad(p);
+  else return p;
+}
+
+// Twiddles of one lane kept in an LDS table laid out [k][L]: entry k of lane l at k * L + l, so
+// the lanes of a line read consecutive words and the lines of a wave share them.
+struct TwStrided {
+  const float2* p;   // table + l
+  int stride;        // L
+  TACAW_HD float2 operator[](int k) const { return p[k * stride]; }
+};
+
+// butterflies of one stage for one lane l; v holds E values striped, tw[TO + ...] the stage's
+// twiddles (a register array or an accessor) for power-of-two lengths, tab the root table otherwise
+template <int N, int L, int R, int NS, bool INV, int TO = 0, class TW>
+TACAW_HD void stage_compute(float2* v, const TW& tw, const float2* tab = nullptr, int l = 0) {
   constexpr int E = N / L, B = E / R;
+  constexpr bool TABLE = (N & (N - 1)) != 0;
 #pragma unroll
   for (int i = 0; i < B; ++i) {
     float2 x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = v[i + B * r];
     if constexpr (NS > 1) {
+      const int m = TABLE ? (l + L * i) % NS : 0;
 #pragma unroll
-      for (int r = 1; r < R; ++r)
-        x[r] = INV ? cmulc(x[r], tw[i * (R - 1) + r - 1]) : cmul(x[r], tw[i * (R - 1) + r - 1]);
+      for (int r = 1; r < R; ++r) {
+        const float2 w = TABLE ? tab[m * r * (N / (NS * R))] : tw[TO + i * (R - 1) + r - 1];
+        x[r] = INV ? cmulc(x[r], w) : cmul(x[r], w);
+      }
     }
     dft<R, INV>(x);
 #pragma unroll
@@ -239,8 +443,10 @@ template <int N, int L, int R, int NS> TACAW_HD void stage_twiddles(float2* tw, 
     int m = b % NS;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      // angle = -2 pi m r / (NS R) -> sinpi/cospi argument -(m r) / (NS R / 2), exact in float
-      float xarg = -(float)(m * r) / (float)(NS * R / 2);
+      // angle = -2 pi m r / (NS R) -> sinpi/cospi argument -(m r) / (NS R / 2) (exact in float
+      // for power-of-two lengths)
+      float xarg = ((NS * R) % 2 == 0) ? -(float)(m * r) / (float)(NS * R / 2)
+                                       : -2.0f * (float)(m * r) / (float)(NS * R);
       float s, c;
       sincospi_f(xarg, &s, &c);
       tw[i * (R - 1) + r - 1] = make_float2(c, s);
@@ -251,12 +457,45 @@ template <int N, int L, int R, int NS> TACAW_HD void stage_twiddles(float2* tw, 
 template <int N, int L, int NS, int R, int... Rest>
 TACAW_HD void plan_twiddles_rec(float2* tw, int l) {
   constexpr int E = N / L;
-  if constexpr (NS > 1) {
+  if constexpr (NS > 1 && E % R == 0 && (N & (N - 1)) == 0) {
     stage_twiddles<N, L, R, NS>(tw, l);
     tw += (E / R) * (R - 1);
   }
   if constexpr (sizeof...(Rest) > 0) plan_twiddles_rec<N, L, NS * R, Rest...>(tw, l);
 }
+
+// In-place last stage of radix R (R need not divide E) for lane l of a line held in lds: the
+// N/R butterflies b read and write b + (N/R) r; lane l takes b = l + L i.  tab[m] = exp(-2 pi i
+// m / N); b r < N, so no reduction is needed.
+template <int N, int L, int R, bool INV>
+TACAW_HD void lds_stage_lane(float2* lds, const float2* tab, int l) {
+  constexpr int NS = N / R;
+  constexpr int ROUNDS = (NS + L - 1) / L;
+#pragma unroll
+  for (int i = 0; i < ROUNDS; ++i) {
+    const int b = l + L * i;
+    if ((NS % L) == 0 || i + 1 < ROUNDS || b < NS) {
+      float2 x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = lds[pad_of<N>(b + NS * r)];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tab[b * r];
+        x[r] = INV ? cmulc(x[r], w) : cmul(x[r], w);
+      }
+      dft<R, INV>(x);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[pad_of<N>(b + NS * r)] = x[r];
+    }
+  }
+}
+
+// whether a plan's remaining radices are exactly one radix that leaves a remainder in E
+template <int E, int... Rest> constexpr bool next_is_lds_stage() {
+  if constexpr (sizeof...(Rest) == 1) return ((E % Rest) + ...) != 0;
+  else return false;
+}
+template <int... Rest> constexpr int only_radix() { return (Rest + ...); }
 
 template <class P> struct PlanOps;
 template <int N, int L, int... Rs> struct PlanOps<Plan<N, L, Rs...>> {
@@ -285,21 +524,31 @@ template <int E, int PRUNE> __device__ __forceinline__ void prune_mid(float2* v,
   }
 }
 
-template <int N, int L, bool INV, int NS, int PRUNE, int R, int... Rest>
-__device__ __forceinline__ void fft_rec(float2* v, const float2* tw, float2* lds, int l) {
+template <int N, int L, bool INV, int NS, int PRUNE, int TO, class TW, int R, int... Rest>
+__device__ __forceinline__ void fft_rec(float2* v, const TW& tw, float2* lds, int l,
+                                        const float2* tab) {
   constexpr int E = N / L, B = E / R;
   if constexpr (NS == 1) prune_mid<E, PRUNE>(v, 1);
-  stage_compute<N, L, R, NS, INV>(v, tw);
+  stage_compute<N, L, R, NS, INV, TO>(v, tw, tab, l);
   if constexpr (sizeof...(Rest) > 0) {
     wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < B; ++i)
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_pad(stage_out_pos<N, L, R, NS>(l, i, r))] = v[i + B * r];
+      for (int r = 0; r < R; ++r) lds[pad_of<N>(stage_out_pos<N, L, R, NS>(l, i, r))] = v[i + B * r];
     wave_lds_sync();
+    if constexpr (next_is_lds_stage<E, Rest...>()) {
+      lds_stage_lane<N, L, only_radix<Rest...>(), INV>(lds, tab, l);
+      wave_lds_sync();
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
-    fft_rec<N, L, INV, NS * R, PRUNE, Rest...>(v, (NS > 1) ? tw + B * (R - 1) : tw, lds, l);
+      for (int j = 0; j < E; ++j) v[j] = lds[pad_of<N>(l + L * j)];
+      prune_mid<E, PRUNE>(v, 2);
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = lds[pad_of<N>(l + L * j)];
+      fft_rec<N, L, INV, NS * R, PRUNE, (NS > 1) ? TO + B * (R - 1) : TO, TW, Rest...>(v, tw, lds, l,
+                                                                                     tab);
+    }
   } else {
     prune_mid<E, PRUNE>(v, 2);
   }
@@ -309,42 +558,67 @@ __device__ __forceinline__ void fft_rec(float2* v, const float2* tw, float2* lds
 // workgroup barrier.  Exchanges alternate between two LDS regions (running parity `buf`); a region
 // is rewritten only two exchanges after it was read, with a barrier in between, so one barrier per
 // exchange suffices.  With lds1 == lds0 (single buffer) a second barrier guards the rewrite.
-template <int N, int L, bool INV, int NS, int PRUNE, int R, int... Rest>
-__device__ __forceinline__ void fft_block_rec(float2* v, const float2* tw, float2* lds0,
-                                              float2* lds1, int l, int& buf) {
+template <int N, int L, bool INV, int NS, int PRUNE, int TO, class TW, int R, int... Rest>
+__device__ __forceinline__ void fft_block_rec(float2* v, const TW& tw, float2* lds0, float2* lds1,
+                                              int l, int& buf) {
   constexpr int E = N / L, B = E / R;
+  static_assert(E % R == 0 && (N & (N - 1)) == 0,
+                "the workgroup variant takes power-of-two lengths (register twiddles)");
   if constexpr (NS == 1) prune_mid<E, PRUNE>(v, 1);
-  stage_compute<N, L, R, NS, INV>(v, tw);
+  stage_compute<N, L, R, NS, INV, TO>(v, tw);
   if constexpr (sizeof...(Rest) > 0) {
     float2* lds = buf ? lds1 : lds0;
 #pragma unroll
     for (int i = 0; i < B; ++i)
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_pad(stage_out_pos<N, L, R, NS>(l, i, r))] = v[i + B * r];
+      for (int r = 0; r < R; ++r) lds[pad_of<N>(stage_out_pos<N, L, R, NS>(l, i, r))] = v[i + B * r];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
+    for (int j = 0; j < E; ++j) v[j] = lds[pad_of<N>(l + L * j)];
     if (lds0 == lds1) __syncthreads();
     buf ^= 1;
-    fft_block_rec<N, L, INV, NS * R, PRUNE, Rest...>(v, (NS > 1) ? tw + B * (R - 1) : tw, lds0, lds1,
-                                                     l, buf);
+    fft_block_rec<N, L, INV, NS * R, PRUNE, (NS > 1) ? TO + B * (R - 1) : TO, TW, Rest...>(
+        v, tw, lds0, lds1, l, buf);
   } else {
     prune_mid<E, PRUNE>(v, 2);
   }
 }
 
+// The workgroup's table of N-th roots of unity for a plan with an LDS last stage.  Every thread of
+// the workgroup calls fft_table_init once before the first transform (it ends with a barrier).
+template <class P> __device__ __forceinline__ float2* fft_table_storage() {
+  __shared__ float2 t[P::TABN > 0 ? P::TABN : 1];
+  return t;
+}
+template <class P> __device__ __forceinline__ const float2* fft_table_init() {
+  if constexpr (P::TABN > 0) {
+    float2* t = fft_table_storage<P>();
+    for (int m = (int)threadIdx.x; m < P::N; m += (int)blockDim.x) {
+      double sn, cs;
+      sincospi(-2.0 * (double)m / (double)P::N, &sn, &cs);
+      t[m] = make_float2((float)cs, (float)sn);
+    }
+    __syncthreads();
+    return t;
+  } else {
+    return nullptr;
+  }
+}
+
 template <class P> struct FFT;
 template <int N, int L, int... Rs> struct FFT<Plan<N, L, Rs...>> {
-  // unnormalised transform of one line held striped in v; lds = this line's exchange region
-  template <bool INV, int PRUNE = 0>
-  __device__ __forceinline__ static void run(float2* v, const float2* tw, float2* lds, int l) {
-    fft_rec<N, L, INV, 1, PRUNE, Rs...>(v, tw, lds, l);
+  // unnormalised transform of one line held striped in v; lds = this line's exchange region;
+  // tab = the workgroup's root table (plans with an LDS last stage only)
+  template <bool INV, int PRUNE = 0, class TW>
+  __device__ __forceinline__ static void run(float2* v, const TW& tw, float2* lds, int l,
+                                             const float2* tab = nullptr) {
+    fft_rec<N, L, INV, 1, PRUNE, 0, TW, Rs...>(v, tw, lds, l, tab);
   }
   // same transform when the line's lanes span several wavefronts of the workgroup
-  template <bool INV, int PRUNE = 0>
-  __device__ __forceinline__ static void run_block(float2* v, const float2* tw, float2* lds0,
+  template <bool INV, int PRUNE = 0, class TW>
+  __device__ __forceinline__ static void run_block(float2* v, const TW& tw, float2* lds0,
                                                    float2* lds1, int l, int& buf) {
-    fft_block_rec<N, L, INV, 1, PRUNE, Rs...>(v, tw, lds0, lds1, l, buf);
+    fft_block_rec<N, L, INV, 1, PRUNE, 0, TW, Rs...>(v, tw, lds0, lds1, l, buf);
   }
 };
 #endif

@@ -1,7 +1,7 @@
 // CPU emulation of the wave-level Stockham FFT in fft.hpp.
 //
 // Every lane of a line is emulated in turn with the very same per-lane functions the kernels use
-// (stage_compute, stage_out_pos, stage_twiddles, lds_pad); the LDS exchange is an array.  The
+// (stage_compute, stage_out_pos, stage_twiddles, pad_of); the LDS exchange is an array.  The
 // result of each plan, forward and inverse, is compared with a double-precision DFT.  Prints one
 // line per plan and exits non-zero on any mismatch.
 #include <cmath>
@@ -17,18 +17,42 @@ using namespace tacaw;
 
 template <int N, int L, bool INV, int NS, int R, int... Rest>
 static void emu_rec(std::vector<float2>& v, std::vector<std::vector<float2>>& tw, int twoff,
-                    std::vector<float2>& lds) {
+                    std::vector<float2>& lds, const std::vector<float2>& tab) {
   constexpr int E = N / L, B = E / R;
-  for (int l = 0; l < L; ++l) stage_compute<N, L, R, NS, INV>(&v[l * E], &tw[l][twoff]);
+  for (int l = 0; l < L; ++l) {
+    const float2* t = &tw[l][twoff];
+    stage_compute<N, L, R, NS, INV>(&v[l * E], t, tab.data(), l);
+  }
   if constexpr (sizeof...(Rest) > 0) {
     for (int l = 0; l < L; ++l)
       for (int i = 0; i < B; ++i)
         for (int r = 0; r < R; ++r)
-          lds[lds_pad(stage_out_pos<N, L, R, NS>(l, i, r))] = v[l * E + i + B * r];
-    for (int l = 0; l < L; ++l)
-      for (int j = 0; j < E; ++j) v[l * E + j] = lds[lds_pad(l + L * j)];
-    emu_rec<N, L, INV, NS * R, Rest...>(v, tw, (NS > 1) ? twoff + B * (R - 1) : twoff, lds);
+          lds[pad_of<N>(stage_out_pos<N, L, R, NS>(l, i, r))] = v[l * E + i + B * r];
+    if constexpr (next_is_lds_stage<E, Rest...>()) {
+      // in-place last stage: the lanes' butterflies touch disjoint positions
+      for (int l = 0; l < L; ++l) lds_stage_lane<N, L, only_radix<Rest...>(), INV>(lds.data(), tab.data(), l);
+      for (int l = 0; l < L; ++l)
+        for (int j = 0; j < E; ++j) v[l * E + j] = lds[pad_of<N>(l + L * j)];
+    } else {
+      for (int l = 0; l < L; ++l)
+        for (int j = 0; j < E; ++j) v[l * E + j] = lds[pad_of<N>(l + L * j)];
+      emu_rec<N, L, INV, NS * R, Rest...>(v, tw, (NS > 1) ? twoff + B * (R - 1) : twoff, lds, tab);
+    }
   }
+}
+
+// every LDS position a lane stage touches lies inside the line's region
+template <int N, int L, int R> static bool lds_stage_in_bounds(int lds_line) {
+  constexpr int NS = N / R, ROUNDS = (NS + L - 1) / L;
+  for (int l = 0; l < L; ++l)
+    for (int i = 0; i < ROUNDS; ++i) {
+      const int b = l + L * i;
+      if (!((NS % L) == 0 || i + 1 < ROUNDS || b < NS)) continue;
+      if (b >= NS) return false;
+      for (int r = 0; r < R; ++r)
+        if (pad_of<N>(b + NS * r) >= lds_line || b * r >= N) return false;
+    }
+  return true;
 }
 
 template <class P> struct Emu;
@@ -49,7 +73,13 @@ template <int N, int L, int... Rs> struct Emu<Plan<N, L, Rs...>> {
     std::vector<std::vector<float2>> tw(L, std::vector<float2>(PL::NTW));
     for (int l = 0; l < L; ++l) PlanOps<PL>::twiddles(tw[l].data(), l);
     std::vector<float2> lds(PL::LDS_LINE);
-    emu_rec<N, L, INV, 1, Rs...>(v, tw, 0, lds);
+    std::vector<float2> tab(N);
+    for (int m = 0; m < N; ++m)
+      tab[m] = make_float2((float)std::cos(-2.0 * M_PI * m / N), (float)std::sin(-2.0 * M_PI * m / N));
+    if constexpr (PL::LDS_LAST) {
+      if (!lds_stage_in_bounds<N, L, PL::radix(PL::NR - 1)>(PL::LDS_LINE)) return 1e30;
+    }
+    emu_rec<N, L, INV, 1, Rs...>(v, tw, 0, lds, tab);
     double err = 0, nrm = 0;
     const double sgn = INV ? 1.0 : -1.0;
     for (int k = 0; k < N; ++k) {
@@ -71,6 +101,11 @@ template <class P> static int check(const char* name) {
   bool ok = ef < 2e-6 && ei < 2e-6;
   std::printf("%-28s N=%5d L=%3d  fwd rel-L2 %.2e  inv rel-L2 %.2e  %s\n", name, P::N, P::L, ef, ei,
               ok ? "ok" : "FAIL");
+  // the exchange writes of every stage stay inside the line's region too
+  if (P::pad(P::N - 1) >= P::LDS_LINE) {
+    std::printf("%-28s LDS line too short\n", name);
+    return 1;
+  }
   return ok ? 0 : 1;
 }
 

@@ -105,6 +105,10 @@ hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStr
 hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st);
 int row_lines_per_wave(int n, int plan);
 int col_lds_bytes(int n, int plan, int C);
+// grid lengths with FFT plans; the root-table LDS of a plan; y-pass kinds a plan supports
+bool grid_size_ok(int n);
+int plan_static_lds(int n, int plan);
+bool plan_kind_ok(int n, int plan, int kind);
 
 // potentials
 hipError_t launch_bin_atoms(const float* xyz, const int* species, int n_snap, int n_atoms,

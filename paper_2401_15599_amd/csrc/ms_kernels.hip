@@ -6,7 +6,8 @@
 //   column kernel, s:     W = G_y[ M P_s F_y W' ] / (nx ny)   (or, after the last slice, the exit
 //                         wave phi = M P_s F_y W' / sqrt(nx ny) stored in (kx, ky))
 // with F/G the unnormalised forward/inverse DFTs.  Each pass reads and writes the wave once (plus V
-// in the row pass), so one slice step moves 36 N^2 bytes through HBM.
+// in the row pass, shared by the probe positions of a snapshot): 32 N^2 bytes per slice step and
+// wave plus 4 N^2 per snapshot, less where the band limit leaves columns out.
 //
 // Row kernel: one line = one image row, held by L lanes of a wave; lines never share LDS, so the
 // transform needs no workgroup barrier.  All probe positions of a snapshot share one load of the V
@@ -28,6 +29,8 @@ template <class F> static bool with_plan(int n, int idx, F&& f) {
     case 256: if (idx == 1) f(P256b{}); else if (idx == 2) f(P256c{}); else f(P256a{}); return true;
     case 512: if (idx == 1) f(P512b{}); else f(P512a{}); return true;
     case 1024: if (idx == 1) f(P1024b{}); else f(P1024a{}); return true;
+    case 560: f(P560a{}); return true;
+    case 1000: f(P1000a{}); return true;
     default: return false;
   }
 }
@@ -36,6 +39,7 @@ int n_plans(int n) {
   switch (n) {
     case 16: case 32: case 64: case 128: case 512: case 1024: return 2;
     case 256: return 3;
+    case 560: case 1000: return 1;
     default: return 0;
   }
 }
@@ -44,12 +48,14 @@ const char* plan_name(int n, int idx) {
   static const char* names[] = {"16:L2:8x2", "16:L4:4x4", "32:L4:8x4", "32:L2:16x2", "64:L8:8x8",
                                 "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "256:L32:8x8x4",
                                 "256:L16:16x16", "256:L64:4x4x4x4", "512:L64:8x8x8",
-                                "512:L32:16x8x4", "1024:L64:16x16x4", "1024:L64:16x4x16"};
+                                "512:L32:16x8x4", "1024:L64:16x16x4", "1024:L64:16x4x16",
+                                "560:L28:4x5x4x7", "1000:L50:4x5x5x10"};
   int base = 0;
   switch (n) {
     case 16: base = 0; break; case 32: base = 2; break; case 64: base = 4; break;
     case 128: base = 6; break; case 256: base = 8; break; case 512: base = 11; break;
-    case 1024: base = 13; break; default: return "?";
+    case 1024: base = 13; break; case 560: base = 15; break; case 1000: base = 16; break;
+    default: return "?";
   }
   if (idx < 0 || idx >= n_plans(n)) return "?";
   return names[base + idx];
@@ -126,10 +132,15 @@ __device__ __forceinline__ void col_task(const ColArgs& a, int task, int tpw, in
   col0 = (jt < a.tiles_lo || a.tiles_hi == 0 ? jt : jt + tpi - a.tiles_lo - a.tiles_hi) * a.C;
 }
 
+// Lengths that are not powers of two ask the compiler for at least 3 wavefronts per SIMD (2 for
+// the adjoint x pass, which holds three line-sized arrays); their transforms would otherwise take
+// every register for instruction-level parallelism.
+template <class P, bool ADJ = false> constexpr int min_waves() { return P::POW2 ? 1 : (ADJ ? 2 : 3); }
+
 // ------------------------------------------------------------------------------------------------
 // x pass
 template <class P, bool ADJ, bool PR = false>
-__global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
+__global__ __launch_bounds__(kThreads, (min_waves<P, ADJ>())) void k_row(RowArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES;
   __shared__ float2 lds_all[kWaves * LINES * P::LDS_LINE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -137,14 +148,17 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
   float2* lds = lds_all + (wave * LINES + line) * P::LDS_LINE;
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
+  const float2* tab = fft_table_init<P>();
 
+  // rows per image: a power of two (shift and mask) or any other length (division)
   const int ny = a.ny, ysh = __builtin_ctz(ny);
-  const int n_tasks = a.n_groups << ysh;
+  const bool ypow2 = (ny & (ny - 1)) == 0;
+  const int n_tasks = a.n_groups * ny;
   const int stride = (int)gridDim.x * kWaves * LINES;
   for (int base = ((int)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
     const int task = base + line;
-    if (task >= n_tasks) continue;
-    const int g = task >> ysh, y = task & (ny - 1);
+    if ((!P::FULL && line >= LINES) || task >= n_tasks) continue;
+    const int g = ypow2 ? task >> ysh : task / ny, y = task - g * ny;
     const int2 gr = const_at(a.groups, g);
     CJob& J = job_at(a.jobs, gr.x);
     const int t = gr.y, s = a.s;
@@ -168,10 +182,11 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
     // read) and of no use on output (not written) when band_in / band_out say so
     const int kxb = J.kxb;
     // bit j: element l + L j is inside the band
-    unsigned inb = 0;
+    typedef std::conditional_t<(E > 32), unsigned long long, unsigned> Mask;
+    Mask inb = 0;
 #pragma unroll
-    for (int j = 0; j < E; ++j) inb |= (in_band(l + L * j, kxb, N) ? 1u : 0u) << j;
-    const unsigned rmask = a.band_in ? inb : ~0u, wmask = a.band_out ? inb : ~0u;
+    for (int j = 0; j < E; ++j) inb |= (in_band(l + L * j, kxb, N) ? Mask(1) : Mask(0)) << j;
+    const Mask rmask = a.band_in ? inb : ~Mask(0), wmask = a.band_out ? inb : ~Mask(0);
     for (int p = 0; p < P_; ++p) {
       const int w = t * P_ + p;
       float2 v[E];
@@ -180,14 +195,14 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
 #pragma unroll
         for (int j = 0; j < E; ++j)
           v[j] = (PR && (j == E / 2 - 1 || j == E / 2)) ? make_float2(0.f, 0.f)
-                                                         : load_if_nt(in + l + L * j, (rmask >> j) & 1u);
+                                                         : load_if_nt(in + l + L * j, (rmask >> j) & 1);
       }
       if (!ADJ && a.store_ckpt) {
         GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j) ck[l + L * j] = v[j];
       }
-      FFT<P>::template run<true, PR ? 1 : 0>(v, tw, lds, l);          // psi_s (real space)
+      FFT<P>::template run<true, PR ? 1 : 0>(v, tw, lds, l, tab);     // psi_s (real space)
       if constexpr (!ADJ) {
         if (a.stash_slot >= 0) {
           GLOBAL_AS float2* st = gp(J.stash) + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
@@ -207,11 +222,11 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
         }
       }
       if (a.write_out) {
-        FFT<P>::template run<false, PR ? 2 : 0>(v, tw, lds, l);
+        FFT<P>::template run<false, PR ? 2 : 0>(v, tw, lds, l, tab);
         GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s) + row;
 #pragma unroll
         for (int j = 0; j < E; ++j)
-          if (!(PR && (j == E / 2 - 1 || j == E / 2)) && ((wmask >> j) & 1u)) store_nt(out + l + L * j, v[j]);
+          if (!(PR && (j == E / 2 - 1 || j == E / 2)) && ((wmask >> j) & 1)) store_nt(out + l + L * j, v[j]);
       }
     }
     if constexpr (ADJ) {
@@ -225,13 +240,14 @@ __global__ __launch_bounds__(kThreads) void k_row(RowArgs a) {
 // ------------------------------------------------------------------------------------------------
 // y pass: optional forward y transform, propagator, optional inverse y transform
 template <class P, bool DOFWD, bool DOINV>
-__global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
+__global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col(ColArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE;
   extern __shared__ float2 tile[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = lane / L, l = lane % L;
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
+  const float2* tab = fft_table_init<P>();
   const int C = a.C, nx = a.nx;
   const int tpi = nx / C, tpw = col_tiles_per_wave(a, tpi);
   const int n_tasks = a.n_waves * tpw;
@@ -247,18 +263,18 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      tile[c * CS + lds_pad(r)] =
+      tile[c * CS + P::pad(r)] =
           load_if(in + (size_t)r * nx + col0 + c, in_band(col0 + c, kxb, nx));
     }
     __syncthreads();
     for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
       const int c = cb + line;
-      if (c < C) {
+      if ((P::FULL || line < LINES) && c < C) {
         float2* lds = tile + c * CS;
         float2 v[E];
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
-        if constexpr (DOFWD) FFT<P>::template run<false>(v, tw, lds, l);
+        for (int j = 0; j < E; ++j) v[j] = lds[P::pad(l + L * j)];
+        if constexpr (DOFWD) FFT<P>::template run<false>(v, tw, lds, l, tab);
         const int m = col0 + c;
         const int nm = gp(J.nmax)[m];
         const float2 pxm = gp(J.px)[(size_t)s * nx + m];
@@ -272,15 +288,15 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
           if (a.conj_prop) d.y = -d.y;
           v[j] = cscale(cmul(v[j], d), a.scale);
         }
-        if constexpr (DOINV) FFT<P>::template run<true>(v, tw, lds, l);
+        if constexpr (DOINV) FFT<P>::template run<true>(v, tw, lds, l, tab);
 #pragma unroll
-        for (int j = 0; j < E; ++j) lds[lds_pad(l + L * j)] = v[j];
+        for (int j = 0; j < E; ++j) lds[P::pad(l + L * j)] = v[j];
       }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      out[(size_t)r * nx + col0 + c] = tile[c * CS + lds_pad(r)];
+      out[(size_t)r * nx + col0 + c] = tile[c * CS + P::pad(r)];
     }
   }
 }
@@ -401,6 +417,8 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
     for (int k = 0; k < NTW; ++k) twl[threadIdx.x * NTW + k] = t[k];
   }
   const float2* tw = twl + l * NTW;
+  const float2* tab = fft_table_init<P>();
+  static_assert(P::FULL, "the staging loops assume whole lines per wavefront");
   const int s = a.s;
   const int tpi = nx / C, tpw = col_tiles_per_wave(a, tpi);
   const int n_tasks = a.n_waves * tpw;
@@ -431,7 +449,7 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int idx = (int)threadIdx.x + k * nthr;
-      tile[(idx & cmask) * CS + lds_pad(idx >> csh)] = nxt[k];
+      tile[(idx & cmask) * CS + P::pad(idx >> csh)] = nxt[k];
     }
     if (wv.x != py_job) {
       const GLOBAL_AS float2* pys = gp(job_at(a.jobs, wv.x).py) + s * N;
@@ -452,8 +470,8 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
       float2* reg = tile + c * CS;
       float2 v[E];
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = reg[lds_pad(l + L * j)];
-      if constexpr (DOFWD) FFT<P>::template run<false, PR ? 2 : 0>(v, tw, reg, l);
+      for (int j = 0; j < E; ++j) v[j] = reg[P::pad(l + L * j)];
+      if constexpr (DOFWD) FFT<P>::template run<false, PR ? 2 : 0>(v, tw, reg, l, tab);
       if constexpr (PR) prune_mid<E, 1>(v, 1);   // M is zero there (also for a raw adjoint input)
       float2 pxs = cscale(pxm, a.scale);
       if (a.conj_prop) pxs.y = -pxs.y;
@@ -465,29 +483,30 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
         if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
         v[j] = cmul(v[j], d);
       }
-      if constexpr (DOINV) FFT<P>::template run<true, PR ? 1 : 0>(v, tw, reg, l);
+      if constexpr (DOINV) FFT<P>::template run<true, PR ? 1 : 0>(v, tw, reg, l, tab);
 #pragma unroll
-      for (int j = 0; j < E; ++j) reg[lds_pad(l + L * j)] = v[j];
+      for (int j = 0; j < E; ++j) reg[P::pad(l + L * j)] = v[j];
     }
     __syncthreads();
     GLOBAL_AS float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s) + col0;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int idx = (int)threadIdx.x + k * nthr;
-      out[(idx >> csh) * nx + (idx & cmask)] = tile[(idx & cmask) * CS + lds_pad(idx >> csh)];
+      out[(idx >> csh) * nx + (idx & cmask)] = tile[(idx & cmask) * CS + P::pad(idx >> csh)];
     }
   }
 }
 
 // probe: psi_0 in the (kx, y) representation, W = G_y[a(k)] / (sqrt(nx ny) sqrt(n_aperture))
 template <class P>
-__global__ __launch_bounds__(kThreads) void k_probe_init(ColArgs a) {
+__global__ __launch_bounds__(kThreads, min_waves<P>()) void k_probe_init(ColArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE;
   extern __shared__ float2 tile[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = lane / L, l = lane % L;
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
+  const float2* tab = fft_table_init<P>();
   const int C = a.C, nx = a.nx;
   const int tpi = nx / C;
   const long n_tasks = (long)a.n_waves * tpi;
@@ -501,7 +520,7 @@ __global__ __launch_bounds__(kThreads) void k_probe_init(ColArgs a) {
     __syncthreads();
     for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
       const int c = cb + line;
-      if (c < C) {
+      if ((P::FULL || line < LINES) && c < C) {
         float2* lds = tile + c * CS;
         const int m = col0 + c;
         const int ms = m < nx / 2 ? m : m - nx;
@@ -525,15 +544,15 @@ __global__ __launch_bounds__(kThreads) void k_probe_init(ColArgs a) {
             v[j] = make_float2((float)cs, (float)sn);
           }
         }
-        FFT<P>::template run<true>(v, tw, lds, l);
+        FFT<P>::template run<true>(v, tw, lds, l, tab);
 #pragma unroll
-        for (int j = 0; j < E; ++j) lds[lds_pad(l + L * j)] = cscale(v[j], J.scale_probe);
+        for (int j = 0; j < E; ++j) lds[P::pad(l + L * j)] = cscale(v[j], J.scale_probe);
       }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      out[(size_t)r * nx + col0 + c] = tile[c * CS + lds_pad(r)];
+      out[(size_t)r * nx + col0 + c] = tile[c * CS + P::pad(r)];
     }
   }
 }
@@ -555,7 +574,7 @@ __global__ __launch_bounds__(kThreads) void k_plane_init(ColArgs a) {
 // ------------------------------------------------------------------------------------------------
 // plain batched 2-D transforms of contiguous images
 template <class P, bool INV, bool REAL_IN, bool REAL_OUT>
-__global__ __launch_bounds__(kThreads) void k_row_plain(PlainArgs a) {
+__global__ __launch_bounds__(kThreads, min_waves<P>()) void k_row_plain(PlainArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES;
   __shared__ float2 lds_all[kWaves * LINES * P::LDS_LINE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -563,11 +582,12 @@ __global__ __launch_bounds__(kThreads) void k_row_plain(PlainArgs a) {
   float2* lds = lds_all + (wave * LINES + line) * P::LDS_LINE;
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
+  const float2* tab = fft_table_init<P>();
   const long n_tasks = (long)a.n_img * a.ny;
   const long stride = (long)gridDim.x * kWaves * LINES;
   for (long base = ((long)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
     const long task = base + line;
-    if (task >= n_tasks) continue;
+    if ((!P::FULL && line >= LINES) || task >= n_tasks) continue;
     const size_t off = (size_t)task * N;
     float2 v[E];
     if constexpr (REAL_IN) {
@@ -579,7 +599,7 @@ __global__ __launch_bounds__(kThreads) void k_row_plain(PlainArgs a) {
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = in[l + L * j];
     }
-    FFT<P>::template run<INV>(v, tw, lds, l);
+    FFT<P>::template run<INV>(v, tw, lds, l, tab);
     if constexpr (REAL_OUT) {
       float* out = (float*)a.out + off;
 #pragma unroll
@@ -593,13 +613,14 @@ __global__ __launch_bounds__(kThreads) void k_row_plain(PlainArgs a) {
 }
 
 template <class P, bool INV>
-__global__ __launch_bounds__(kThreads) void k_col_plain(PlainArgs a) {
+__global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col_plain(PlainArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE;
   extern __shared__ float2 tile[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = lane / L, l = lane % L;
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
+  const float2* tab = fft_table_init<P>();
   const int C = a.C, nx = a.nx;
   const int tpi = nx / C;
   const long n_tasks = (long)a.n_img * tpi;
@@ -611,25 +632,25 @@ __global__ __launch_bounds__(kThreads) void k_col_plain(PlainArgs a) {
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      tile[c * CS + lds_pad(r)] = in[(size_t)r * nx + col0 + c];
+      tile[c * CS + P::pad(r)] = in[(size_t)r * nx + col0 + c];
     }
     __syncthreads();
     for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
       const int c = cb + line;
-      if (c < C) {
+      if ((P::FULL || line < LINES) && c < C) {
         float2* lds = tile + c * CS;
         float2 v[E];
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds[lds_pad(l + L * j)];
-        FFT<P>::template run<INV>(v, tw, lds, l);
+        for (int j = 0; j < E; ++j) v[j] = lds[P::pad(l + L * j)];
+        FFT<P>::template run<INV>(v, tw, lds, l, tab);
 #pragma unroll
-        for (int j = 0; j < E; ++j) lds[lds_pad(l + L * j)] = v[j];
+        for (int j = 0; j < E; ++j) lds[P::pad(l + L * j)] = v[j];
       }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      out[(size_t)r * nx + col0 + c] = tile[c * CS + lds_pad(r)];
+      out[(size_t)r * nx + col0 + c] = tile[c * CS + P::pad(r)];
     }
   }
 }
@@ -657,7 +678,7 @@ hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hip
       hipLaunchKernelGGL((k_row<P, true>), dim3(grid), dim3(kThreads), 0, st, a);
     } else {
       bool done = false;
-      if constexpr (P::E >= 8) {
+      if constexpr (P::E >= 8 && P::POW2) {
         if (a.prune) {
           hipLaunchKernelGGL((k_row<P, false, true>), dim3(grid), dim3(kThreads), 0, st, a);
           done = true;
@@ -676,14 +697,41 @@ bool plan_prunable(int n, int plan, int kb) {
   bool ok = false;
   with_plan(n, plan, [&](auto p) {
     using P = decltype(p);
-    ok = P::E >= 8 && kb <= P::N / 2 - P::L - 1;
+    ok = P::E >= 8 && P::POW2 && kb <= P::N / 2 - P::L - 1;
+  });
+  return ok;
+}
+
+// grid sizes with FFT plans: powers of two 16..1024 and the odd-factor lengths
+const int kGridSizes[] = {16, 32, 64, 128, 256, 512, 1024, 560, 1000};
+
+bool grid_size_ok(int n) {
+  for (int g : kGridSizes)
+    if (g == n) return true;
+  return false;
+}
+
+// LDS a plan's kernels hold besides their dynamic tile (the root table of an LDS last stage)
+int plan_static_lds(int n, int plan) {
+  int b = 0;
+  with_plan(n, plan, [&](auto p) { b = decltype(p)::TABN * (int)sizeof(float2); });
+  return b;
+}
+
+// which y-pass kinds a plan supports: 0 always; 1 (workgroup exchanges, register twiddles) a
+// power-of-two length; 2 (wave per column) whole lines per wavefront
+bool plan_kind_ok(int n, int plan, int kind) {
+  bool ok = false;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    ok = kind == 0 || (kind == 1 && P::POW2) || (kind == 2 && P::FULL);
   });
   return ok;
 }
 
 // Dynamic LDS limits are raised once per context creation (never during graph capture).
 void prepare_dynamic_lds(int max_bytes) {
-  for (int n = 16; n <= 1024; n *= 2)
+  for (int n : kGridSizes)
     for (int idx = 0; idx < n_plans(n); ++idx)
       with_plan(n, idx, [&](auto p) {
         using P = decltype(p);
@@ -692,13 +740,17 @@ void prepare_dynamic_lds(int max_bytes) {
         (void)hipFuncSetAttribute((const void*)k_col<P, true, false>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col<P, false, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_probe_init<P>, (hipFuncAttribute)attr, max_bytes);
-        (void)hipFuncSetAttribute((const void*)k_colb<P, true, true>, (hipFuncAttribute)attr, max_bytes);
-        (void)hipFuncSetAttribute((const void*)k_colb<P, true, false>, (hipFuncAttribute)attr, max_bytes);
-        (void)hipFuncSetAttribute((const void*)k_colb<P, false, true>, (hipFuncAttribute)attr, max_bytes);
-        (void)hipFuncSetAttribute((const void*)k_colw<P, true, true>, (hipFuncAttribute)attr, max_bytes);
-        (void)hipFuncSetAttribute((const void*)k_colw<P, true, false>, (hipFuncAttribute)attr, max_bytes);
-        (void)hipFuncSetAttribute((const void*)k_colw<P, false, true>, (hipFuncAttribute)attr, max_bytes);
-        if constexpr (P::E >= 8) {
+        if constexpr (P::POW2) {
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, false>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, false, true>, (hipFuncAttribute)attr, max_bytes);
+        }
+        if constexpr (P::FULL) {
+          (void)hipFuncSetAttribute((const void*)k_colw<P, true, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colw<P, true, false>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colw<P, false, true>, (hipFuncAttribute)attr, max_bytes);
+        }
+        if constexpr (P::E >= 8 && P::POW2) {
           (void)hipFuncSetAttribute((const void*)k_colb<P, true, true, true>, (hipFuncAttribute)attr, max_bytes);
           (void)hipFuncSetAttribute((const void*)k_colb<P, true, false, true>, (hipFuncAttribute)attr, max_bytes);
           (void)hipFuncSetAttribute((const void*)k_colb<P, false, true, true>, (hipFuncAttribute)attr, max_bytes);
@@ -742,7 +794,7 @@ int col_wave_threads(int n, int plan, int C) {
     using P = decltype(p);
     t = (C / P::LINES) * 64;
     // every wavefront must own LINES whole columns, within the kernel's launch bound
-    if (C % P::LINES != 0 || t > colw_max_threads<P>()) t = 1 << 30;
+    if (!P::FULL || C % P::LINES != 0 || t > colw_max_threads<P>()) t = 1 << 30;
   });
   return t;
 }
@@ -753,53 +805,63 @@ hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const C
   if (kind == 2) {
     with_plan(n, plan, [&](auto p) {
       using P = decltype(p);
-      const int lds = col_wave_lds_bytes(n, plan, a.C);
-      const int threads = col_wave_threads(n, plan, a.C);
-      auto go = [&](auto pr) {
-        constexpr bool PR = decltype(pr)::value;
-        if (dofwd && doinv)
-          hipLaunchKernelGGL((k_colw<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
-        else if (dofwd)
-          hipLaunchKernelGGL((k_colw<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
-        else
-          hipLaunchKernelGGL((k_colw<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
-      };
-      bool done = false;
-      if constexpr (P::E >= 8) {
-        if (a.prune) {
-          go(std::true_type{});
-          done = true;
+      if constexpr (!P::FULL) {
+        e = hipErrorInvalidValue;
+        return;
+      } else {
+        const int lds = col_wave_lds_bytes(n, plan, a.C);
+        const int threads = col_wave_threads(n, plan, a.C);
+        auto go = [&](auto pr) {
+          constexpr bool PR = decltype(pr)::value;
+          if (dofwd && doinv)
+            hipLaunchKernelGGL((k_colw<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+          else if (dofwd)
+            hipLaunchKernelGGL((k_colw<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
+          else
+            hipLaunchKernelGGL((k_colw<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+        };
+        bool done = false;
+        if constexpr (P::E >= 8 && P::POW2) {
+          if (a.prune) {
+            go(std::true_type{});
+            done = true;
+          }
         }
+        if (!done) go(std::false_type{});
+        e = hipGetLastError();
       }
-      if (!done) go(std::false_type{});
-      e = hipGetLastError();
     });
     return e;
   }
   if (kind == 1) {
     with_plan(n, plan, [&](auto p) {
       using P = decltype(p);
-      const int lds = ((a.pingpong ? 2 : 1) * a.C * P::LDS_LINE + P::L * P::NTW + P::N) *
-                      (int)sizeof(float2);
-      const int threads = a.C * P::L;
-      auto go = [&](auto pr) {
-        constexpr bool PR = decltype(pr)::value;
-        if (dofwd && doinv)
-          hipLaunchKernelGGL((k_colb<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
-        else if (dofwd)
-          hipLaunchKernelGGL((k_colb<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
-        else
-          hipLaunchKernelGGL((k_colb<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
-      };
-      bool done = false;
-      if constexpr (P::E >= 8) {
-        if (a.prune) {
-          go(std::true_type{});
-          done = true;
+      if constexpr (!P::POW2) {
+        e = hipErrorInvalidValue;
+        return;
+      } else {
+        const int lds = ((a.pingpong ? 2 : 1) * a.C * P::LDS_LINE + P::L * P::NTW + P::N) *
+                        (int)sizeof(float2);
+        const int threads = a.C * P::L;
+        auto go = [&](auto pr) {
+          constexpr bool PR = decltype(pr)::value;
+          if (dofwd && doinv)
+            hipLaunchKernelGGL((k_colb<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+          else if (dofwd)
+            hipLaunchKernelGGL((k_colb<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
+          else
+            hipLaunchKernelGGL((k_colb<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+        };
+        bool done = false;
+        if constexpr (P::E >= 8 && P::POW2) {
+          if (a.prune) {
+            go(std::true_type{});
+            done = true;
+          }
         }
+        if (!done) go(std::false_type{});
+        e = hipGetLastError();
       }
-      if (!done) go(std::false_type{});
-      e = hipGetLastError();
     });
     return e;
   }
@@ -833,10 +895,13 @@ hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+// columns per tile of the plain column transform: a power of two that divides nx
 static int plain_cols(int nx, int n) {
   int c = (n <= 64) ? 64 : (n <= 256 ? 32 : 16);
-  if (n == 1024) c = 8;
-  return c > nx ? nx : c;
+  if (n >= 1000) c = 8;
+  if (c > nx) c = nx;
+  while (c > 1 && nx % c != 0) c /= 2;
+  return c;
 }
 
 hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hipStream_t st) {

@@ -201,6 +201,9 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
   if (map >= a.n_maps) return;
   const int TW = min(kTile, a.nx), TH = min(kTile, a.ny);
   const int m0 = (tile % tx_n) * TW, n0 = (tile / tx_n) * TH;
+  // the last tile of an axis whose length is not a multiple of 64 is partial: kx < TWe, ky < THe
+  // (rows below ny/2 only in Hermitian mode)
+  const int TWe = min(TW, a.nx - m0), THe = min(TH, (herm ? a.ny / 2 : a.ny) - n0);
   const int t = a.t0 + map / a.s_count, s = map % a.s_count;
   const int tid = threadIdx.x;
   for (int i = tid; i < a.n_species * 12; i += 256) ffs[i] = a.ff[i];
@@ -211,22 +214,22 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
       out[(size_t)(a.ny - n) * a.nx + (a.nx - m) % a.nx] = make_float2(v.x, -v.y);
   };
   if (herm && n0 == 0)
-    for (int m = m0 + tid; m < m0 + TW; m += 256)
+    for (int m = m0 + tid; m < m0 + TWe; m += 256)
       out[(size_t)(a.ny / 2) * a.nx + m] = make_float2(0.f, 0.f);
 
   // does any k of this tile pass the band limit?  (exact integer table)
   int any = 0;
   {
     int minabs_n = 1 << 30;
-    for (int n = n0; n < n0 + TH; ++n) {
+    for (int n = n0; n < n0 + THe; ++n) {
       int ns = n < a.ny / 2 ? n : n - a.ny;
       minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
     }
-    for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
+    for (int m = m0 + tid; m < m0 + TWe; m += 256) any |= (a.nmax[m] >= minabs_n);
   }
   any = __syncthreads_or(any);
   if (!any) {
-    for (int i = tid; i < TW * TH; i += 256) put(n0 + i / TW, m0 + i % TW, make_float2(0.f, 0.f));
+    for (int i = tid; i < TWe * THe; i += 256) put(n0 + i / TWe, m0 + i % TWe, make_float2(0.f, 0.f));
     return;
   }
 
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
           const int rem = i % (kSfChunk * (kTile / 8));
           const int at = rem / (kTile / 8), k0 = (rem % (kTile / 8)) * 8;
           float2* dst = axis == 0 ? &ex[at][k0] : &ey[at][k0];
-          const int lim = axis == 0 ? TW : TH;
+          const int lim = axis == 0 ? TWe : THe;
           if (at >= na || k0 >= lim) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) dst[q] = make_float2(0.f, 0.f);
@@ -283,11 +286,14 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
           const int nn = axis == 0 ? a.nx : a.ny;
           const int idx = (axis == 0 ? m0 : n0) + k0;
           const int sidx = idx < nn / 2 ? idx : idx - nn;
+          const int qw = nn / 2 - idx;      // the signed index jumps to -nn/2 at step qw
           const AtomPhase& ap = arec[at];
-          float2 f = phase_factor(sidx, axis == 0 ? ap.ux : ap.uy);
+          const unsigned U = axis == 0 ? ap.ux : ap.uy;
+          float2 f = phase_factor(sidx, U);
           const float2 st = axis == 0 ? ap.sx : ap.sy;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
+            if (q == qw) f = phase_factor(idx + q - nn, U);
             dst[q] = f;
             f = cmul(f, st);
           }
@@ -296,17 +302,26 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
         // one item per thread: (axis, block of 8 k, atom pair); components stored as packed
         // (atom 2p, atom 2p+1) half pairs
         const int axis = tid >> 7, k0 = ((tid >> 4) & 7) * 8, pair = tid & 15;
-        const int lim = axis == 0 ? TW : TH;
+        const int lim = axis == 0 ? TWe : THe;
         const int nn = axis == 0 ? a.nx : a.ny;
         const int idx = (axis == 0 ? m0 : n0) + k0;
         const int sidx = idx < nn / 2 ? idx : idx - nn;
+        // the signed index jumps to -nn/2 at step qw; only a length with nn/2 not a multiple of 8
+        // has a block that straddles the jump (then the factor is restarted exactly there)
+        const int qw = nn / 2 - idx;
+        const bool wraps = qw > 0 && qw < 8;
         float2 f[2], st[2];
+        unsigned Ua[2];
+        bool live[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const int at = 2 * pair + u;
-          if (at < na && k0 < lim) {
+          live[u] = at < na && k0 < lim;
+          Ua[u] = 0u;
+          if (live[u]) {
             const AtomPhase& ap = arec[at];
-            f[u] = phase_factor(sidx, axis == 0 ? ap.ux : ap.uy);
+            Ua[u] = axis == 0 ? ap.ux : ap.uy;
+            f[u] = phase_factor(sidx, Ua[u]);
             st[u] = axis == 0 ? ap.sx : ap.sy;
           } else {
             f[u] = make_float2(0.f, 0.f);
@@ -318,6 +333,11 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
         _Float16* row = tb + axis * 4 * kTabH + 2 * pair;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
+          if (wraps && q == qw) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+              if (live[u]) f[u] = phase_factor(idx + q - nn, Ua[u]);
+          }
           const h2 rh = __builtin_amdgcn_cvt_pkrtz(f[0].x, f[1].x);
           const h2 ih = __builtin_amdgcn_cvt_pkrtz(f[0].y, f[1].y);
           const h2 rl = __builtin_amdgcn_cvt_pkrtz(f[0].x - (float)rh[0], f[1].x - (float)rh[1]);
@@ -386,13 +406,13 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
     }
   }
   const int tj = 32 * wx + li;
-  if (tj < TW) {
+  if (tj < TWe) {
     const int m = m0 + tj;
     const int nm = a.nmax[m];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ti = 32 * wy + (r & 3) + 4 * lk + 8 * (r >> 2);
-      if (ti >= TH) continue;
+      if (ti >= THe) continue;
       const int n = n0 + ti, ns = n < a.ny / 2 ? n : n - a.ny, an = ns < 0 ? -ns : ns;
       put(n, m, an <= nm ? make_float2(vr[r] * a.pref, vi[r] * a.pref) : make_float2(0.f, 0.f));
     }
@@ -488,7 +508,7 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
   const int ny_h = herm ? a.ny / 2 : a.ny;
   const float* vt = a.vtab + (size_t)z * ny_h * a.nx;
   const int TW = min(kTile, a.nx);
-  const int tx_n = a.nx / TW;
+  const int tx_n = (a.nx + TW - 1) / TW;
   // power-of-two scale of H for this map
   float hs = 1.f;
   {
@@ -506,6 +526,7 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
 
   for (int tx = 0; tx < tx_n; ++tx) {
     const int m0 = tx * TW;
+    const int TWe = min(TW, a.nx - m0);   // the last kx tile of a length not a multiple of 64
     v16f cr = {0}, ci = {0}, tr = {0}, ti = {0};
     int used = 0;
     for (int n0 = 0; n0 < ny_h; n0 += kPgKy) {
@@ -516,7 +537,7 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
         minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
       }
       int any = 0;
-      for (int m = m0 + tid; m < m0 + TW; m += 256) any |= (a.nmax[m] >= minabs_n);
+      for (int m = m0 + tid; m < m0 + TWe; m += 256) any |= (a.nmax[m] >= minabs_n);
       if (!__syncthreads_or(any)) continue;     // also: the previous fill's readers are done
       used = 1;
       // H and ky H for (kx = m0 + c, ky rows n0 + 8 kb + q): 8 consecutive ky per thread
@@ -529,7 +550,7 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
           const int n = n0 + 8 * kb + q;
           float2 h = make_float2(0.f, 0.f);
           float ky = 0.f;
-          if (c < TW && n < n0 + kh) {
+          if (c < TWe && n < n0 + kh) {
             const int ns = n < a.ny / 2 ? n : n - a.ny;
             ky = (float)ns / (float)a.ly;
             const float v = vt[(size_t)n * a.nx + m] * hs;
@@ -560,14 +581,17 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
         const int at = tid & 63, kb = tid >> 6;
         const int n = n0 + 8 * kb;
         const int sidx = n < a.ny / 2 ? n : n - a.ny;
+        const int qw = a.ny / 2 - n;            // the signed index jumps to -ny/2 at step qw
+        const bool live = at < na && 8 * kb < kh;
         float2 f = make_float2(0.f, 0.f), st = make_float2(0.f, 0.f);
-        if (at < na && 8 * kb < kh) {
+        if (live) {
           f = phase_factor(sidx, rec[at].uy);
           st = rec[at].sy;
         }
         v8h rh, ih, rl, il;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
+          if (q == qw && live) f = phase_factor(n + q - a.ny, rec[at].uy);
           const _Float16 a_hi = (_Float16)f.x, b_hi = (_Float16)f.y;
           rh[q] = a_hi;
           ih[q] = b_hi;
@@ -630,16 +654,18 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
     for (int i = tid; i < kChunk * (kTile / 8); i += 256) {
       const int at = i / (kTile / 8), kb = (i % (kTile / 8)) * 8;
       float2* dst = &Ex[at][kb];
-      if (at >= na || kb >= TW) {
+      if (at >= na || kb >= TWe) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) dst[q] = make_float2(0.f, 0.f);
         continue;
       }
       const int idx = m0 + kb, sidx = idx < a.nx / 2 ? idx : idx - a.nx;
+      const int qw = a.nx / 2 - idx;           // the signed index jumps to -nx/2 at step qw
       float2 ph = phase_factor(sidx, rec[at].ux);
       const float2 st = rec[at].sx;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
+        if (q == qw) ph = phase_factor(idx + q - a.nx, rec[at].ux);
         dst[q] = ph;
         ph = cmul(ph, st);
       }

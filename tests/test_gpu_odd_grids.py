@@ -1,0 +1,233 @@
+"""GPU parity on grids whose lengths are not powers of two: 560 (= 2^4 5 7, the grid of the
+paper's Si and hBN runs, Sec. III) and 1000 (= 2^3 5^3, the Fe grid of the magnon example).
+
+Their transforms use plans with odd radices and an in-place LDS last stage; every step of the
+path (potentials, both beams, the uneven batch, the spectrum, the adjoint and the position
+gradient) is compared with the FP64 oracle at the same tolerances as the power-of-two grids.
+"""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+import paper_2401_15599_amd as tw
+from paper_2401_15599_amd.autograd import TacawMultislice, TacawPotentials, TacawSpectrum
+from oracle import adjoint as o_adj
+from oracle import multislice as o_ms
+from oracle import potential as o_pot
+from oracle import spectrum as o_sp
+from workloads import form_factor_table
+
+DEV = "cuda:0"
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def check(a, b, tol, what=""):
+    e = rel_l2(a, b)
+    assert e <= tol, f"{what} rel-L2 {e:.3e} > {tol:g}"
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _specimen(nx, ny, lx, ly, dz, n_atoms, n_snap, seed, bandlimit=2.0 / 3.0):
+    rng = np.random.default_rng(seed)
+    zt = float(np.sum(dz))
+    pos = np.stack([rng.uniform(-0.5, lx + 0.5, size=(n_snap, n_atoms)),
+                    rng.uniform(-0.5, ly + 0.5, size=(n_snap, n_atoms)),
+                    rng.uniform(0.0, zt, size=(n_snap, n_atoms))], axis=-1).astype(np.float32)
+    species = rng.integers(0, 2, size=n_atoms).astype(np.int32)
+    spec = SimpleNamespace(nx=nx, ny=ny, lx=lx, ly=ly, dz=np.asarray(dz, float), z0=0.0,
+                           bandlimit=bandlimit)
+    return spec, pos, species
+
+
+# ------------------------------------------------------------------------------------------------
+# potentials: partial 64-wide k tiles, the +-N/2 wrap inside a block of 8 (1000/2 = 500), the
+# half-plane and full-plane contractions
+
+@pytest.mark.parametrize("split16", [1, 0])
+@pytest.mark.parametrize("case", ["560-half", "1000-half", "1000x64-full", "64x1000-full",
+                                  "560x1000-half"])
+def test_potentials_odd_grids(case, split16):
+    if case == "560-half":
+        spec, pos, sp = _specimen(560, 560, 54.3, 54.3, [2.0, 1.5], 300, 1, 41)
+    elif case == "1000-half":
+        spec, pos, sp = _specimen(1000, 1000, 57.4, 57.4, [2.0], 400, 1, 42)
+    elif case == "1000x64-full":
+        spec, pos, sp = _specimen(1000, 64, 90.0, 6.0, [2.0, 2.5], 200, 2, 43, bandlimit=0.0)
+    elif case == "64x1000-full":
+        spec, pos, sp = _specimen(64, 1000, 6.0, 90.0, [2.0, 2.5], 200, 2, 44, bandlimit=0.0)
+    else:
+        spec, pos, sp = _specimen(560, 1000, 40.0, 71.0, [3.0], 300, 1, 45)
+    ff = form_factor_table(["A", "B"])
+    V = torch.empty((pos.shape[0], len(spec.dz), spec.ny, spec.nx), dtype=torch.float32, device=DEV)
+    cx = tw.Context(0)
+    tw.tacaw_set_potential_precision(cx, split16)
+    tw.tacaw_build_potentials(cx, tw.specimen_from(spec), _gpu(pos), _gpu(sp), ff, V)
+    ref, _ = o_pot.potentials(pos, sp, ff, spec)
+    check(V.cpu().numpy(), ref, 1e-5, case)
+
+
+# ------------------------------------------------------------------------------------------------
+# multislice
+
+def _exit(spec, beam, V32, mode=tw.MODE_BATCHED, ctx=None):
+    n_pos = len(beam.probe_xy) if beam.probe else 1
+    out = torch.empty((V32.shape[0], n_pos, spec.ny, spec.nx), dtype=torch.complex64, device=DEV)
+    out.fill_(float("nan"))
+    tw.tacaw_multislice(ctx or tw.context(0),
+                        [tw.MsJob(tw.specimen_from(spec), tw.beam_from(beam), _gpu(V32), out)],
+                        mode=mode)
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [560, 1000])
+@pytest.mark.parametrize("mode", [tw.MODE_BATCHED, tw.MODE_PLAIN])
+def test_multislice_plane_wave_odd_grid(n, mode):
+    spec, pos, sp = _specimen(n, n, n * 0.097, n * 0.097, [2.0] * (3 if n == 560 else 2), 300, 1, 51)
+    V, _ = o_pot.potentials(pos, sp, form_factor_table(["A", "B"]), spec)
+    V32 = V.astype(np.float32)
+    beam = SimpleNamespace(probe=False, energy_ev=100e3)
+    got = _exit(spec, beam, V32, mode)
+    ref = o_ms.exit_waves(V32.astype(np.float64), spec, beam)
+    check(got, ref, 1e-4, f"{n} plane wave")
+
+
+@pytest.mark.parametrize("nx,ny", [(560, 560), (560, 128), (128, 1000)])
+def test_multislice_probe_odd_grid(nx, ny):
+    spec, pos, sp = _specimen(nx, ny, nx * 0.09, ny * 0.09, [2.0, 2.0], 200, 2, 52)
+    V, _ = o_pot.potentials(pos, sp, form_factor_table(["A", "B"]), spec)
+    V32 = V.astype(np.float32)
+    beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.030, defocus_a=20.0, cs_a=0.0,
+                           probe_xy=np.array([[nx * 0.045, ny * 0.045], [3.3, 4.1]]))
+    got = _exit(spec, beam, V32)
+    ref = o_ms.exit_waves(V32.astype(np.float64), spec, beam)
+    for t in range(2):
+        for p in range(2):
+            check(got[t, p], ref[t, p], 1e-4, f"{nx}x{ny} t={t} p={p}")
+
+
+def test_uneven_batch_with_odd_and_power_of_two_classes():
+    ff = form_factor_table(["A", "B"])
+    cases = [_specimen(560, 560, 54.0, 54.0, [2.0] * 3, 250, 2, 61),
+             _specimen(560, 560, 50.0, 54.0, [2.0] * 1, 250, 1, 62),
+             _specimen(64, 64, 16.0, 16.0, [2.0] * 4, 60, 2, 63),
+             _specimen(1000, 32, 80.0, 3.0, [1.5] * 2, 80, 1, 64)]
+    beam = SimpleNamespace(probe=False, energy_ev=100e3)
+    jobs, outs, refs = [], [], []
+    for spec, pos, sp in cases:
+        V32 = o_pot.potentials(pos, sp, ff, spec)[0].astype(np.float32)
+        refs.append(o_ms.exit_waves(V32.astype(np.float64), spec, beam))
+        out = torch.empty((V32.shape[0], 1, spec.ny, spec.nx), dtype=torch.complex64, device=DEV)
+        outs.append(out)
+        jobs.append(tw.MsJob(tw.specimen_from(spec), tw.Beam(100e3), _gpu(V32), out))
+    for mode in (tw.MODE_BATCHED, tw.MODE_PLAIN):
+        for out in outs:
+            out.fill_(float("nan"))
+        tw.tacaw_multislice(tw.context(0), jobs, mode=mode)
+        for k, (out, ref) in enumerate(zip(outs, refs)):
+            check(out.cpu().numpy(), ref, 1e-4, f"job {k} mode {mode}")
+
+
+def test_autotuned_odd_grid_schedule_matches_oracle(tmp_path):
+    cx = tw.Context(0)
+    for n in (560, 1000):
+        tw.tacaw_autotune(cx, n, 4, str(tmp_path / "tune.jsonl"))
+        assert tw.tacaw_describe_schedule(cx, n)
+    spec, pos, sp = _specimen(560, 560, 54.0, 54.0, [2.0] * 2, 250, 1, 71)
+    V32 = o_pot.potentials(pos, sp, form_factor_table(["A", "B"]), spec)[0].astype(np.float32)
+    beam = SimpleNamespace(probe=False, energy_ev=100e3)
+    check(_exit(spec, beam, V32, ctx=cx), o_ms.exit_waves(V32.astype(np.float64), spec, beam), 1e-4)
+
+
+# ------------------------------------------------------------------------------------------------
+# spectrum
+
+def test_spectrum_odd_grid():
+    rng = np.random.default_rng(8)
+    T, P, ny, nx = 32, 2, 16, 560
+    ex = (rng.normal(size=(T, P, ny, nx)) + 1j * rng.normal(size=(T, P, ny, nx))).astype(np.complex64)
+    opts = tw.SpectrumOpts(5.0, 300.0, 16, 8, 301, 13)
+    S = torch.empty((16, 13, 301), dtype=torch.float32, device=DEV)
+    norm = torch.empty((1,), dtype=torch.float64, device=DEV)
+    tw.tacaw_autocorr_spectrum(tw.context(0), _gpu(ex), opts, S, norm)
+    ref, Z = o_sp.spectrum(ex.astype(np.complex128), 16, 8, 5.0, 300.0, 13, 301)
+    check(S.cpu().numpy(), ref, 1e-3)
+    assert abs(norm.item() - Z) <= 1e-5 * Z
+
+
+def test_spectrum_rejects_ragged_q_tiles():
+    # 1000^2 q points are not a whole number of the 128-q tiles the 16-point time plan uses
+    ex = torch.zeros((16, 1, 1000, 1000), dtype=torch.complex64, device=DEV)
+    P = torch.empty((16, 1000, 1000), dtype=torch.float32, device=DEV)
+    with pytest.raises(RuntimeError, match="multiple of"):
+        tw.tacaw_periodogram(tw.context(0), ex, 16, 16, P)
+
+
+# ------------------------------------------------------------------------------------------------
+# adjoint and position gradient
+
+@pytest.mark.parametrize("nx,ny", [(560, 32), (32, 1000)])
+def test_adjoint_odd_grid(nx, ny):
+    spec, pos, sp = _specimen(nx, ny, nx * 0.1, ny * 0.1, [2.0] * 4, 60, 2, 81)
+    V32 = o_pot.potentials(pos, sp, form_factor_table(["A", "B"]), spec)[0].astype(np.float32)
+    beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.05, defocus_a=10.0, cs_a=0.0,
+                           probe_xy=np.array([[2.0, 1.0], [5.5, 2.25]]))
+    rng = np.random.default_rng(9)
+    T, S, stride = 2, 4, 2
+    out = torch.empty((T, 2, ny, nx), dtype=torch.complex64, device=DEV)
+    ck = torch.empty((T, 2, 2, ny, nx), dtype=torch.complex64, device=DEV)
+    job = tw.MsJob(tw.specimen_from(spec), tw.beam_from(beam), _gpu(V32), out, ck)
+    g = ((rng.normal(size=(T, 2, ny, nx)) + 1j * rng.normal(size=(T, 2, ny, nx))) * 1e-2).astype(np.complex64)
+    gV = torch.empty(V32.shape, dtype=torch.float32, device=DEV)
+    cx = tw.context(0)
+    tw.tacaw_multislice(cx, [job], ckpt_stride=stride)
+    tw.tacaw_multislice_adjoint(cx, [job], stride, [_gpu(g)], [gV])
+    psi0 = o_ms.initial_waves(spec, beam)
+    ref = np.zeros(V32.shape)
+    for t in range(T):
+        for p in range(2):
+            ref[t] += o_adj.multislice_adjoint(psi0[p], V32[t].astype(np.float64), spec,
+                                               beam.energy_ev, g[t, p].astype(np.complex128))
+    check(gV.cpu().numpy(), ref, 1e-3, f"{nx}x{ny} dL/dV")
+
+
+@pytest.mark.parametrize("nx,ny", [(560, 32), (128, 1000)])
+def test_pipeline_gradient_odd_grid(nx, ny):
+    rng = np.random.default_rng(3)
+    lx, ly = nx * 0.25, ny * 0.22
+    dz = np.array([2.0, 2.0, 2.0])
+    n_at, T = 24, 16
+    base = np.column_stack([rng.uniform(0, lx, n_at), rng.uniform(0, ly, n_at),
+                            rng.choice([1.0, 3.0, 5.0], n_at)])
+    pos = (base[None] + 0.1 * rng.normal(size=(T, n_at, 3)) * [1, 1, 0]).astype(np.float32)
+    species = rng.integers(0, 2, n_at).astype(np.int32)
+    spec = SimpleNamespace(nx=nx, ny=ny, lx=lx, ly=ly, dz=dz, z0=0.0, bandlimit=2.0 / 3.0)
+    beam = SimpleNamespace(probe=False, energy_ev=100e3)
+    ff = form_factor_table(["A", "B"])
+    n_e, hop, dt = 16, 16, 5.0
+    emask = o_adj.energy_filter_mask(n_e, dt, 0.0, 0.2)
+    target = rng.uniform(0, 0.01, size=(ny, nx))
+    ref = o_adj.pipeline_gradient(pos, species, ff, spec, beam, n_e, hop, dt, 300.0, target, emask)
+    tspec = tw.specimen_from(spec)
+    xyz = _gpu(pos).requires_grad_(True)
+    V = TacawPotentials.apply(xyz, _gpu(species), tspec, ff)
+    V.retain_grad()
+    ex = TacawMultislice.apply(V, tspec, tw.Beam(100e3), 2)
+    S = TacawSpectrum.apply(ex, tw.SpectrumOpts(dt, 300.0, n_e, hop, nx, ny))
+    em = torch.from_numpy(emask).to(DEV)
+    tg = torch.from_numpy(target.astype(np.float32)).to(DEV)
+    loss = ((S[em].sum(0) - tg) ** 2).sum()
+    loss.backward()
+    assert abs(loss.item() - ref["loss"]) <= 1e-3 * ref["loss"]
+    check(V.grad.cpu().numpy(), ref["gV"], 1e-3, "dL/dV")
+    check(xyz.grad.cpu().numpy()[..., :2], ref["gxy"], 1e-3, "dL/dxy")

@@ -50,3 +50,13 @@ def test_fft_plans_cpu_emulation():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout
     assert "FFT host check passed" in r.stdout
+    # the odd-length plans (radices 4, 5, 7 and 10 with an in-place LDS last stage) are covered
+    assert "n560" in r.stdout and "n1000" in r.stdout
+
+
+def test_plan_counts_cover_the_supported_grids():
+    import paper_2401_15599_amd as tw
+    for n in (16, 32, 64, 128, 256, 512, 1024, 560, 1000):
+        assert tw.tacaw_plan_count(n) >= 1, n
+    for n in (8, 48, 600, 2048):
+        assert tw.tacaw_plan_count(n) == 0, n
