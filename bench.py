@@ -200,6 +200,70 @@ def plane_wave_leg(tw):
                 slice_steps=steps, median_ms=med * 1e3, slice_steps_per_s=steps / med)
 
 
+def odd_grid_leg(tw):
+    """Secondary lines on the grids of the paper's own runs, whose lengths are not powers of two
+    (synthetic stand-ins, multislice only, median of 3 timed calls after one warm-up call):
+      * 560^2: silicon-like diamond crystal, 7 x 7 x 23 cubic cells (a = 5.4773 A; a quarter of
+        the paper's 92-cell thickness), 184 slices of a/8, 60 keV plane wave, 64 snapshots at
+        25 fs (trajectory seed 7001);
+      * 1000^2: iron-like bcc crystal, 20 x 20 x 4 cells (a = 2.87 A), 120 slices of a/30,
+        200 keV probe of 1 mrad at one position, 32 snapshots at 4 fs (seed 7002).
+    Per-pass rates are the algorithmic bytes of the x and y passes over their kernel time."""
+    import torch
+    from workloads.configs import make_workload
+    from workloads.trajectory import harmonic_trajectory
+    out = {}
+    legs = [
+        ("si_560", dict(kind="diamond", a=5.4773, reps=(7, 7, 23), n=(560, 560), n_slices=184,
+                        dz=5.4773 / 8, energy=60e3, T=64, dt=25.0, n_e=64, hop=64, seed=7001,
+                        probe=False, alpha=0.0),
+         "plane wave 60 keV, silicon-like 7x7x23 cells, 560^2, 184 slices, 64 snapshots"),
+        ("fe_1000", dict(kind="bcc", a=2.87, reps=(20, 20, 4), n=(1000, 1000), n_slices=120,
+                         dz=2.87 / 30, energy=200e3, T=32, dt=4.0, n_e=32, hop=32, seed=7002,
+                         probe=True, alpha=1e-3),
+         "probe 200 keV 1 mrad, iron-like bcc 20x20x4 cells, 1000^2, 120 slices, 32 snapshots"),
+    ]
+    for key, cfg, desc in legs:
+        ctx = tw.Context(0)
+        w = make_workload(cfg, generate=False, name=key)
+        if w.probe:
+            w.probe_xy = w.probe_xy[:1]
+        T = cfg["T"]
+        xyz = harmonic_trajectory(w.extra["structure"], T, cfg["dt"], cfg["seed"], device="cuda:0")
+        sp = tw.specimen_from(w)
+        V = torch.empty((T, w.n_slices, w.ny, w.nx), dtype=torch.float32, device="cuda:0")
+        tw.tacaw_build_potentials(ctx, sp, xyz, torch.from_numpy(w.species).to("cuda:0"), w.ff, V)
+        del xyz
+        n_pos = len(w.probe_xy) if w.probe else 1
+        ex = torch.empty((T, n_pos, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+        job = [tw.MsJob(sp, tw.beam_from(w), V, ex)]
+        tw.tacaw_multislice(ctx, job, mode=tw.MODE_BATCHED)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            tw.tacaw_multislice(ctx, job, mode=tw.MODE_BATCHED)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        tw.tacaw_set_timing(ctx, True)
+        tw.tacaw_multislice(ctx, job, mode=tw.MODE_BATCHED)
+        torch.cuda.synchronize()
+        kinds = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col")}
+        tw.tacaw_set_timing(ctx, False)
+        med = sorted(times)[len(times) // 2]
+        steps = T * n_pos * w.n_slices
+        out[key] = dict(
+            workload=desc, slice_steps=steps, median_ms=med * 1e3, slice_steps_per_s=steps / med,
+            pixel_slice_steps_per_s=steps * w.nx * w.ny / med,
+            pass_GBps={k: (v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] else None
+                       for k, v in kinds.items()},
+            pass_ms={k: v["total_ms"] for k, v in kinds.items()},
+            schedule=tw.tacaw_describe_schedule(ctx, w.nx))
+        del V, ex, job, ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def structure_factor_work(ws):
     """Complex multiply-adds the structure-factor contraction needs per step: for every map, the
     band-limited k points of the computed half plane (ky >= 0, the rest is the conjugate
@@ -385,6 +449,11 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] homogeneous plane-wave leg")
         extra["plane_wave_512"] = plane_wave_leg(tw)
+        extra["plane_wave_512"]["pixel_slice_steps_per_s"] = (
+            extra["plane_wave_512"]["slice_steps_per_s"] * 512 * 512)
+        torch.cuda.empty_cache()
+        log("[bench] odd-length grid legs (560^2, 1000^2)")
+        extra["odd_grids"] = odd_grid_leg(tw)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline (host cores)")

@@ -10,7 +10,8 @@
  * Units: lengths in Angstrom, energies of the beam in eV, potentials in V*Angstrom (projected per
  *   slice), times in fs, temperatures in K.
  * Complex data: tacaw_c64 (interleaved float re, im).  Real data: float.  Positions: float x, y, z.
- * Grids: nx, ny are powers of two in [16, 1024]; images are row-major [ny][nx] (x fastest).
+ * Grids: nx, ny are powers of two in [16, 1024], or 560 or 1000 (each axis independently; the
+ * grids of the paper's Si/hBN and Fe runs); images are row-major [ny][nx] (x fastest).
  *   Reciprocal-space images use DFT storage order: index m holds kx = m/Lx for m < nx/2 and
  *   (m - nx)/Lx otherwise (likewise for y).
  * Memory: "dev" pointers are device memory on the context's GPU, owned by the caller (for instance
@@ -68,7 +69,7 @@ const char* tacaw_last_error(void);
  * time step and the (q, E) output grid).
  */
 typedef struct {
-  int32_t nx, ny;          /* grid, powers of two in [16, 1024] */
+  int32_t nx, ny;          /* grid: powers of two in [16, 1024], 560 or 1000 */
   double lx, ly;           /* orthorhombic cell, periodic in x and y (Angstrom) */
   int32_t n_slices;        /* S >= 1 */
   const double* dz;        /* host [S] slice thicknesses (Angstrom), > 0 */
@@ -207,7 +208,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
 typedef struct {
   double dt_fs;            /* snapshot spacing (fs) */
   double temperature_k;    /* > 0 */
-  int32_t n_e;             /* segment length = energy bins, power of two in [8, 4096] */
+  int32_t n_e;             /* segment length = energy bins, power of two in [16, 1024] */
   int32_t hop;             /* segment offset >= 1 */
   int32_t nqx_out, nqy_out;/* centred crop, 1..nx and 1..ny */
 } tacaw_spectrum_opts;
@@ -216,7 +217,8 @@ typedef struct {
  *   exit   dev [n_snap][n_pos][ny][nx]
  *   P_acc  dev [n_e][ny][nx] float; overwritten when accumulate == 0, added to otherwise (use this
  *          to sum probe positions processed in chunks).
- * Errors: TACAW_E_ARG, TACAW_E_SIZE (n_e), TACAW_E_HIP. */
+ * Errors: TACAW_E_ARG, TACAW_E_SIZE (n_e; or nx * ny not a multiple of the q tile of the time
+ * kernels: 128 for n_e = 16, 64 for 32, 32 for 64, 16 above), TACAW_E_HIP. */
 int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
                       const tacaw_c64* exit, int32_t n_e, int32_t hop, float* P_acc,
                       int32_t accumulate, void* stream);
@@ -254,9 +256,11 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
                    void* stream);
 /* Load tuning choices previously written by tacaw_autotune (host, synchronous).  One JSON object
  * per line: {"n": grid, "row": x-pass plan, "col": y-pass plan, "C": columns per tile (power of
- * two <= 64), "kind": y-pass kernel (0 staged, 1 workgroup-exchange block, 2 wave-per-column),
- * "pp": ping-pong exchange buffers of kind 1 (0/1)}.  C is reduced at launch to what fits the
- * grid, the workgroup and the LDS.  A missing file is not an error.
+ * two <= 64 dividing n), "kind": y-pass kernel (0 staged, 1 workgroup-exchange block, 2
+ * wave-per-column; 2 only for plans whose lines fill a wavefront, i.e. not for 560 and 1000),
+ * "pp": ping-pong exchange buffers of kind 1 (0/1)}.  C is reduced at launch to what divides the
+ * image width and fits the workgroup and the LDS; a wave-per-column request that no width can
+ * serve runs the staged kind.  A missing file is not an error.
  * Errors: TACAW_E_ARG (malformed file). */
 int tacaw_load_tuning(tacaw_ctx* ctx, const char* cache_path);
 /* Number of compiled FFT plans (radix chains and lanes per line) for grid size n, 0 if none. */

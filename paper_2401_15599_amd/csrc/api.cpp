@@ -342,11 +342,9 @@ Sched schedule_for(tacaw_ctx* c, int n) {
   if (it != c->sched.end()) return it->second;
   // built-in choices: tacaw_autotune on an MI355X over 1 GiB batches of waves per grid size
   // {n, row plan, column plan, C, kind, pp}
-  // (560 and 1000: the staged y pass, the one kind their plans' LDS last stage leaves open to
-  // every column count)
   static const int table[][6] = {{16, 1, 1, 16, 1, 1},  {32, 0, 0, 16, 2, 0},  {64, 0, 0, 64, 1, 0},
                                  {128, 0, 0, 32, 1, 0}, {256, 0, 1, 32, 2, 0}, {512, 0, 0, 16, 1, 1},
-                                 {1024, 0, 0, 8, 2, 0}, {560, 0, 0, 16, 0, 0},  {1000, 0, 0, 8, 0, 0}};
+                                 {1024, 0, 0, 8, 2, 0}, {560, 0, 0, 16, 1, 0},  {1000, 0, 0, 8, 1, 1}};
   Sched s;
   s.row_plan = 0;
   s.col_plan = 0;
@@ -373,7 +371,7 @@ Sched fit_cols(tacaw_ctx* c, int ny, Sched s, int nx) {
   const int budget = c->max_lds - plan_static_lds(ny, s.col_plan);
   if (s.col_kind == 1) {
     const int L = plan_lanes(ny, s.col_plan);
-    while (s.C > 1 && s.C * L > 1024) s.C /= 2;
+    while (s.C > 1 && s.C * L > col_block_max_threads(ny, s.col_plan)) s.C /= 2;
     if (s.pp && col_block_lds_bytes(ny, s.col_plan, s.C, 1) > budget) s.pp = 0;
     while (s.C > 1 && col_block_lds_bytes(ny, s.col_plan, s.C, s.pp) > budget) s.C /= 2;
   } else if (s.col_kind == 2) {
@@ -1369,11 +1367,11 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
     for (int cpn = 0; cpn < n_plans(n); ++cpn)
       for (int kind = 0; kind < 3; ++kind)
       for (int pp = 0; pp < (kind == 1 ? 2 : 1); ++pp)
-      for (int C = 8; C <= 64; C *= 2) {
+      for (int C = 4; C <= 64; C *= 2) {
         if (C > n || n % C != 0 || !plan_kind_ok(n, cpn, kind)) continue;
         const int budget = ctx->max_lds - plan_static_lds(n, cpn);
         if (kind == 0 && col_lds_bytes(n, cpn, C) > budget) continue;
-        if (kind == 1 && (C * plan_lanes(n, cpn) > 1024 ||
+        if (kind == 1 && (C * plan_lanes(n, cpn) > col_block_max_threads(n, cpn) ||
                           col_block_lds_bytes(n, cpn, C, pp) > budget)) continue;
         if (kind == 2 && (col_wave_threads(n, cpn, C) > 1024 ||
                           col_wave_lds_bytes(n, cpn, C) > budget)) continue;

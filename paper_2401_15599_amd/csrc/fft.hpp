@@ -558,14 +558,15 @@ __device__ __forceinline__ void fft_rec(float2* v, const TW& tw, float2* lds, in
 // workgroup barrier.  Exchanges alternate between two LDS regions (running parity `buf`); a region
 // is rewritten only two exchanges after it was read, with a barrier in between, so one barrier per
 // exchange suffices.  With lds1 == lds0 (single buffer) a second barrier guards the rewrite.
+// (An LDS last stage runs in place between the exchange's write and its read, with a barrier on
+// either side; the region's reuse distance is unchanged.)
 template <int N, int L, bool INV, int NS, int PRUNE, int TO, class TW, int R, int... Rest>
 __device__ __forceinline__ void fft_block_rec(float2* v, const TW& tw, float2* lds0, float2* lds1,
-                                              int l, int& buf) {
+                                              int l, int& buf, const float2* tab) {
   constexpr int E = N / L, B = E / R;
-  static_assert(E % R == 0 && (N & (N - 1)) == 0,
-                "the workgroup variant takes power-of-two lengths (register twiddles)");
+  static_assert(E % R == 0, "register stages take radices that divide E");
   if constexpr (NS == 1) prune_mid<E, PRUNE>(v, 1);
-  stage_compute<N, L, R, NS, INV, TO>(v, tw);
+  stage_compute<N, L, R, NS, INV, TO>(v, tw, tab, l);
   if constexpr (sizeof...(Rest) > 0) {
     float2* lds = buf ? lds1 : lds0;
 #pragma unroll
@@ -573,12 +574,22 @@ __device__ __forceinline__ void fft_block_rec(float2* v, const TW& tw, float2* l
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[pad_of<N>(stage_out_pos<N, L, R, NS>(l, i, r))] = v[i + B * r];
     __syncthreads();
+    if constexpr (next_is_lds_stage<E, Rest...>()) {
+      lds_stage_lane<N, L, only_radix<Rest...>(), INV>(lds, tab, l);
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = lds[pad_of<N>(l + L * j)];
-    if (lds0 == lds1) __syncthreads();
-    buf ^= 1;
-    fft_block_rec<N, L, INV, NS * R, PRUNE, (NS > 1) ? TO + B * (R - 1) : TO, TW, Rest...>(
-        v, tw, lds0, lds1, l, buf);
+      for (int j = 0; j < E; ++j) v[j] = lds[pad_of<N>(l + L * j)];
+      if (lds0 == lds1) __syncthreads();
+      buf ^= 1;
+      prune_mid<E, PRUNE>(v, 2);
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = lds[pad_of<N>(l + L * j)];
+      if (lds0 == lds1) __syncthreads();
+      buf ^= 1;
+      fft_block_rec<N, L, INV, NS * R, PRUNE, (NS > 1) ? TO + B * (R - 1) : TO, TW, Rest...>(
+          v, tw, lds0, lds1, l, buf, tab);
+    }
   } else {
     prune_mid<E, PRUNE>(v, 2);
   }
@@ -617,8 +628,9 @@ template <int N, int L, int... Rs> struct FFT<Plan<N, L, Rs...>> {
   // same transform when the line's lanes span several wavefronts of the workgroup
   template <bool INV, int PRUNE = 0, class TW>
   __device__ __forceinline__ static void run_block(float2* v, const TW& tw, float2* lds0,
-                                                   float2* lds1, int l, int& buf) {
-    fft_block_rec<N, L, INV, 1, PRUNE, 0, TW, Rs...>(v, tw, lds0, lds1, l, buf);
+                                                   float2* lds1, int l, int& buf,
+                                                   const float2* tab = nullptr) {
+    fft_block_rec<N, L, INV, 1, PRUNE, 0, TW, Rs...>(v, tw, lds0, lds1, l, buf, tab);
   }
 };
 #endif

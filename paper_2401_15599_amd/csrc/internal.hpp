@@ -96,6 +96,7 @@ hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hip
 hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const ColArgs& a, int grid,
                       hipStream_t st);
 int col_block_lds_bytes(int n, int plan, int C, int pingpong);
+int col_block_max_threads(int n, int plan);   // launch bound of the block kind (C * L threads)
 bool plan_prunable(int n, int plan, int kb);
 // kind 2: LDS-staged tile, one line per wavefront lane group, C * 64 / LINES threads
 int col_wave_lds_bytes(int n, int plan, int C);

@@ -29,7 +29,7 @@ template <class F> static bool with_plan(int n, int idx, F&& f) {
     case 256: if (idx == 1) f(P256b{}); else if (idx == 2) f(P256c{}); else f(P256a{}); return true;
     case 512: if (idx == 1) f(P512b{}); else f(P512a{}); return true;
     case 1024: if (idx == 1) f(P1024b{}); else f(P1024a{}); return true;
-    case 560: f(P560a{}); return true;
+    case 560: if (idx == 1) f(P560b{}); else f(P560a{}); return true;
     case 1000: f(P1000a{}); return true;
     default: return false;
   }
@@ -39,7 +39,8 @@ int n_plans(int n) {
   switch (n) {
     case 16: case 32: case 64: case 128: case 512: case 1024: return 2;
     case 256: return 3;
-    case 560: case 1000: return 1;
+    case 560: return 2;
+    case 1000: return 1;
     default: return 0;
   }
 }
@@ -49,12 +50,12 @@ const char* plan_name(int n, int idx) {
                                 "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "256:L32:8x8x4",
                                 "256:L16:16x16", "256:L64:4x4x4x4", "512:L64:8x8x8",
                                 "512:L32:16x8x4", "1024:L64:16x16x4", "1024:L64:16x4x16",
-                                "560:L28:4x5x4x7", "1000:L50:4x5x5x10"};
+                                "560:L28:4x5x4x7", "560:L56:2x5x2x2x14", "1000:L50:4x5x5x10"};
   int base = 0;
   switch (n) {
     case 16: base = 0; break; case 32: base = 2; break; case 64: base = 4; break;
     case 128: base = 6; break; case 256: base = 8; break; case 512: base = 11; break;
-    case 1024: base = 13; break; case 560: base = 15; break; case 1000: base = 16; break;
+    case 1024: base = 13; break; case 560: base = 15; break; case 1000: base = 17; break;
     default: return "?";
   }
   if (idx < 0 || idx >= n_plans(n)) return "?";
@@ -306,8 +307,12 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col(ColArgs a) {
 // segments.  The next tile is prefetched into registers while the current one is transformed.
 // Twiddles live in a small LDS table (lanes sharing l read the same entry); the per-row propagator
 // factors py stay in registers across tiles of the same job.
+// (lengths that are not powers of two: at most 512 threads and 2 wavefronts per SIMD, which leaves
+// their longer lines and table twiddles enough registers)
+template <class P> constexpr int colb_max_threads() { return P::POW2 ? 1024 : 512; }
+
 template <class P, bool DOFWD, bool DOINV, bool PR = false>
-__global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
+__global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_colb(ColArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, CS = P::LDS_LINE, NTW = P::NTW;
   extern __shared__ float2 lds_mem[];
   const int C = a.C, nx = a.nx;
@@ -317,12 +322,13 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
   float2* twl = lds_mem + (a.pingpong ? 2 : 1) * C * CS;
   float2* pyl = twl + L * NTW;                       // [N] propagator factors of the current job
   if (c == 0) {
-    float2 t[NTW];
+    float2 t[NTW] = {};
     PlanOps<P>::twiddles(t, l);
 #pragma unroll
     for (int k = 0; k < NTW; ++k) twl[l * NTW + k] = t[k];
   }
   const float2* tw = twl + l * NTW;
+  const float2* tab = fft_table_init<P>();   // (lengths that are not powers of two)
   int buf = 0;
   const int s = a.s;
   const int tpi = nx / C, tpw = col_tiles_per_wave(a, tpi);
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
       py_job = wv.x;
     }
     if (task + (int)gridDim.x < n_tasks) load(task + gridDim.x);
-    if constexpr (DOFWD) FFT<P>::template run_block<false, PR ? 2 : 0>(v, tw, reg0, reg1, l, buf);
+    if constexpr (DOFWD) FFT<P>::template run_block<false, PR ? 2 : 0>(v, tw, reg0, reg1, l, buf, tab);
     if constexpr (PR) prune_mid<E, 1>(v, 1);   // M is zero there (also for a raw adjoint input)
     {
       // band-limited propagator (conjugated for the adjoint; pyl is stored conjugated then)
@@ -384,7 +390,7 @@ __global__ __launch_bounds__(1024) void k_colb(ColArgs a) {
         v[j] = cmul(v[j], d);
       }
     }
-    if constexpr (DOINV) FFT<P>::template run_block<true, PR ? 1 : 0>(v, tw, reg0, reg1, l, buf);
+    if constexpr (DOINV) FFT<P>::template run_block<true, PR ? 1 : 0>(v, tw, reg0, reg1, l, buf, tab);
     CJob& J = job_at(a.jobs, wv.x);
     GLOBAL_AS float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s);
 #pragma unroll
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
   const int line = lane / L, l = lane % L;
   const int c = wave * LINES + line;              // column of the tile owned by this line
   if (threadIdx.x < L) {
-    float2 t[NTW];
+    float2 t[NTW] = {};
     PlanOps<P>::twiddles(t, threadIdx.x);
 #pragma unroll
     for (int k = 0; k < NTW; ++k) twl[threadIdx.x * NTW + k] = t[k];
@@ -718,13 +724,13 @@ int plan_static_lds(int n, int plan) {
   return b;
 }
 
-// which y-pass kinds a plan supports: 0 always; 1 (workgroup exchanges, register twiddles) a
-// power-of-two length; 2 (wave per column) whole lines per wavefront
+// which y-pass kinds a plan supports: 0 and 1 always; 2 (wave per column) whole lines per
+// wavefront
 bool plan_kind_ok(int n, int plan, int kind) {
   bool ok = false;
   with_plan(n, plan, [&](auto p) {
     using P = decltype(p);
-    ok = kind == 0 || (kind == 1 && P::POW2) || (kind == 2 && P::FULL);
+    ok = kind == 0 || kind == 1 || (kind == 2 && P::FULL);
   });
   return ok;
 }
@@ -740,11 +746,9 @@ void prepare_dynamic_lds(int max_bytes) {
         (void)hipFuncSetAttribute((const void*)k_col<P, true, false>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col<P, false, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_probe_init<P>, (hipFuncAttribute)attr, max_bytes);
-        if constexpr (P::POW2) {
-          (void)hipFuncSetAttribute((const void*)k_colb<P, true, true>, (hipFuncAttribute)attr, max_bytes);
-          (void)hipFuncSetAttribute((const void*)k_colb<P, true, false>, (hipFuncAttribute)attr, max_bytes);
-          (void)hipFuncSetAttribute((const void*)k_colb<P, false, true>, (hipFuncAttribute)attr, max_bytes);
-        }
+        (void)hipFuncSetAttribute((const void*)k_colb<P, true, true>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colb<P, true, false>, (hipFuncAttribute)attr, max_bytes);
+        (void)hipFuncSetAttribute((const void*)k_colb<P, false, true>, (hipFuncAttribute)attr, max_bytes);
         if constexpr (P::FULL) {
           (void)hipFuncSetAttribute((const void*)k_colw<P, true, true>, (hipFuncAttribute)attr, max_bytes);
           (void)hipFuncSetAttribute((const void*)k_colw<P, true, false>, (hipFuncAttribute)attr, max_bytes);
@@ -768,6 +772,12 @@ int plan_lanes(int n, int plan) {
   int L = 0;
   with_plan(n, plan, [&](auto p) { L = decltype(p)::L; });
   return L;
+}
+
+int col_block_max_threads(int n, int plan) {
+  int t = 0;
+  with_plan(n, plan, [&](auto p) { t = colb_max_threads<decltype(p)>(); });
+  return t;
 }
 
 int col_block_lds_bytes(int n, int plan, int C, int pingpong) {
@@ -836,32 +846,27 @@ hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const C
   if (kind == 1) {
     with_plan(n, plan, [&](auto p) {
       using P = decltype(p);
-      if constexpr (!P::POW2) {
-        e = hipErrorInvalidValue;
-        return;
-      } else {
-        const int lds = ((a.pingpong ? 2 : 1) * a.C * P::LDS_LINE + P::L * P::NTW + P::N) *
-                        (int)sizeof(float2);
-        const int threads = a.C * P::L;
-        auto go = [&](auto pr) {
-          constexpr bool PR = decltype(pr)::value;
-          if (dofwd && doinv)
-            hipLaunchKernelGGL((k_colb<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
-          else if (dofwd)
-            hipLaunchKernelGGL((k_colb<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
-          else
-            hipLaunchKernelGGL((k_colb<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
-        };
-        bool done = false;
-        if constexpr (P::E >= 8 && P::POW2) {
-          if (a.prune) {
-            go(std::true_type{});
-            done = true;
-          }
+      const int lds = ((a.pingpong ? 2 : 1) * a.C * P::LDS_LINE + P::L * P::NTW + P::N) *
+                      (int)sizeof(float2);
+      const int threads = a.C * P::L;
+      auto go = [&](auto pr) {
+        constexpr bool PR = decltype(pr)::value;
+        if (dofwd && doinv)
+          hipLaunchKernelGGL((k_colb<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+        else if (dofwd)
+          hipLaunchKernelGGL((k_colb<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
+        else
+          hipLaunchKernelGGL((k_colb<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+      };
+      bool done = false;
+      if constexpr (P::E >= 8 && P::POW2) {
+        if (a.prune) {
+          go(std::true_type{});
+          done = true;
         }
-        if (!done) go(std::false_type{});
-        e = hipGetLastError();
       }
+      if (!done) go(std::false_type{});
+      e = hipGetLastError();
     });
     return e;
   }

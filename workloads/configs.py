@@ -15,7 +15,7 @@ from typing import List, Optional
 import numpy as np
 
 from .formfactors import form_factor_table
-from .structures import fcc_cubic, rocksalt, hexagonal_bn_like
+from .structures import bcc_cubic, diamond_cubic, fcc_cubic, hexagonal_bn_like, rocksalt
 from .trajectory import harmonic_trajectory
 
 
@@ -108,6 +108,10 @@ def _structure(cfg):
         return rocksalt(cfg["a"], cfg["reps"])
     if cfg["kind"] == "hbn":
         return hexagonal_bn_like(cfg["a"], cfg["c"], cfg["reps"])
+    if cfg["kind"] == "diamond":
+        return diamond_cubic(cfg["a"], cfg["reps"])
+    if cfg["kind"] == "bcc":
+        return bcc_cubic(cfg["a"], cfg["reps"])
     raise ValueError(cfg["kind"])
 
 

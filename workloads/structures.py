@@ -70,3 +70,24 @@ def hexagonal_bn_like(a=2.50, c=6.66, reps=(16, 9, 10)):
     pos, s = _tile(basis, spc, (a, b, c), reps)
     pos[:, 2] += c / 4.0
     return Structure(pos, s, ("BN-B", "BN-N"), (a * reps[0], b * reps[1], c * reps[2]), a, c / 2.0)
+
+
+def diamond_cubic(a=5.4773, reps=(7, 7, 92)):
+    """Diamond-structure crystal of one species "A" (silicon-like): two fcc lattices offset by
+    (a/4, a/4, a/4).  Atomic planes every a/4 along z, shifted by a/16 so that they sit inside a
+    slice for slice thicknesses of a/4 or a/8 (the paper's Si runs use 8 slices per cubic cell)."""
+    fcc = [(0, 0, 0), (0.5, 0.5, 0), (0.5, 0, 0.5), (0, 0.5, 0.5)]
+    basis = fcc + [(x + 0.25, y + 0.25, z + 0.25) for (x, y, z) in fcc]
+    pos, spc = _tile(basis, [0] * 8, (a, a, a), reps)
+    pos[:, 2] += a / 16.0
+    return Structure(pos, spc, ("A",), (a * reps[0], a * reps[1], a * reps[2]), a, a / 4.0)
+
+
+def bcc_cubic(a=2.87, reps=(20, 20, 10)):
+    """Body-centred cubic crystal of one species "B" (iron-like); planes every a/2 along z,
+    shifted by a/8 (inside a slice for thicknesses a/2 down to a/4, and for the thin slices of
+    multislice runs whose planes are resolved by several slices)."""
+    basis = [(0, 0, 0), (0.5, 0.5, 0.5)]
+    pos, spc = _tile(basis, [0, 0], (a, a, a), reps)
+    pos[:, 2] += a / 8.0
+    return Structure(pos, spc, ("B",), (a * reps[0], a * reps[1], a * reps[2]), a, a / 2.0)
