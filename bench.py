@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--profile-slice-step", action="store_true",
                    help="short run for counter collection: one batched 512^2 multislice call of "
                         "the workload (8 snapshots) and a 1 GiB device copy as HBM calibration")
+    p.add_argument("--odd-grids-only", action="store_true",
+                   help="run only the 560^2 and 1000^2 lines (for kernel traces of their passes)")
     return p.parse_args()
 
 
@@ -365,6 +367,10 @@ def main():
     args = parse()
     if args.profile_slice_step:
         profile_slice_step(args)
+        return
+    if args.odd_grids_only:
+        import paper_2401_15599_amd as tw
+        print(json.dumps({"odd_grids": odd_grid_leg(tw)}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
