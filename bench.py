@@ -198,8 +198,39 @@ def plane_wave_leg(tw):
         times.append(time.perf_counter() - t0)
     med = sorted(times)[len(times) // 2]
     steps = T * w.n_slices
+    # analysis outputs of the same exit waves: spectrum, energy-integrated patterns, QEP patterns
+    # (all snapshots and every 16th), the q_y = 0 relative-difference profile and a Gamma-X-M-Gamma
+    # dispersion cut; the c~ pattern must equal the all-snapshot QEP pattern (one segment)
+    n_e = 256
+    opts = tw.SpectrumOpts(w.dt_fs, 300.0, n_e, n_e, w.nx, w.ny)
+    P = torch.empty((n_e, w.ny, w.nx), dtype=torch.float32, device="cuda:0")
+    S = torch.empty_like(P)
+    ct, c, q_all, q16 = (torch.empty((w.ny, w.nx), dtype=torch.float32, device="cuda:0") for _ in range(4))
+    prof = torch.empty(w.nx, dtype=torch.float32, device="cuda:0")
+    a = 4.0
+    verts = [(0.0, 0.0), (1.0 / a, 0.0), (1.0 / a, 1.0 / a), (0.0, 0.0)]
+    cut = torch.empty((n_e, 3 * 64 + 1), dtype=torch.float32, device="cuda:0")
+    steps_an = [
+        ("periodogram", lambda: tw.tacaw_periodogram(ctx, ex, n_e, n_e, P)),
+        ("finalize", lambda: tw.tacaw_spectrum_finalize(ctx, P, opts, S)),
+        ("energy_integrals", lambda: tw.tacaw_energy_integrals(ctx, P, opts, ct, c)),
+        ("qep_all", lambda: tw.tacaw_qep_pattern(ctx, ex, 0, 1, T, q_all)),
+        ("qep_every_16th", lambda: tw.tacaw_qep_pattern(ctx, ex, 0, 16, T // 16, q16)),
+        ("relative_difference", lambda: tw.tacaw_relative_difference(ctx, c, q16, prof)),
+        ("path_cut", lambda: tw.tacaw_path_cut(ctx, w.lx, w.ly, S, verts, 64, cut)),
+    ]
+    an_ms = {}
+    for name, f in steps_an:
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f()
+        torch.cuda.synchronize()
+        an_ms[name] = (time.perf_counter() - t0) * 1e3
+    parseval = float(((ct - q_all).abs().max() / q_all.abs().max()).item())
     return dict(workload="plane wave, rocksalt 40x40x20 cells, 512^2, 40 slices, 256 snapshots",
-                slice_steps=steps, median_ms=med * 1e3, slice_steps_per_s=steps / med)
+                slice_steps=steps, median_ms=med * 1e3, slice_steps_per_s=steps / med,
+                analysis_ms=an_ms, parseval_max_rel_diff=parseval)
 
 
 def odd_grid_leg(tw):

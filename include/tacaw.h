@@ -247,6 +247,48 @@ int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int
                                      tacaw_c64* grad_exit, void* stream);
 
 /* ----------------------------------------------------------------------------------------------
+ * Analysis outputs of the spectra (Sec. III, Figs. 1 and 2).  Every sum runs in a fixed order
+ * (float64, no atomics); maps are centred and cropped like the spectrum (index i holds the signed
+ * frequency i - nq/2).  Asynchronous on `stream`; the library's workspace holds the per-q sums.
+ * Errors: TACAW_E_ARG, TACAW_E_SIZE (n_e), TACAW_E_NOMEM, TACAW_E_HIP.
+ *
+ * Energy-integrated diffraction patterns of an accumulated periodogram (the method's patterns of
+ * Fig. 1): c_tilde(q) = sum_k P(q, k) before the Kubo correction and c(q) = sum_k K(E_k) P(q, k)
+ * after it, each divided by its total over the full nx x ny grid.  By Parseval's theorem the first
+ * equals the QEP pattern of the same snapshots when the segments do not overlap.
+ *   P_acc         dev [n_e][ny][nx] float, DFT order (tacaw_periodogram)
+ *   opts          n_e, dt_fs, temperature_k and the crop nqx_out x nqy_out are used
+ *   c_tilde, c    dev out [nqy_out][nqx_out] float; either may be NULL */
+int tacaw_energy_integrals(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* P_acc,
+                           const tacaw_spectrum_opts* opts, float* c_tilde, float* c,
+                           void* stream);
+
+/* QEP (quantum excitation of phonons) pattern: |phi(q)|^2 summed over the snapshots t0 + j t_stride
+ * (j < t_count) and all probe positions, divided by its total over the full grid (the standard
+ * frozen-snapshot average the paper compares against, e.g. 100 evenly spaced snapshots or all).
+ *   exit  dev [n_snap][n_pos][ny][nx];  out dev [nqy_out][nqx_out] float */
+int tacaw_qep_pattern(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
+                      const tacaw_c64* exit, int32_t t0, int32_t t_stride, int32_t t_count,
+                      int32_t nqx_out, int32_t nqy_out, float* out, void* stream);
+
+/* Line profile of Fig. 1: out[i] = (A - B) / (A + B) along the q_y = 0 row (index nqy / 2) of two
+ * centred maps of the same crop; 0 where A + B = 0.
+ *   A, B  dev [nqy][nqx] float;  out_row dev [nqx] float */
+int tacaw_relative_difference(tacaw_ctx* ctx, int32_t nqx, int32_t nqy, const float* A,
+                              const float* B, float* out_row, void* stream);
+
+/* Dispersion cut of Fig. 2: S(q, E) along the polyline through `vertices` (host [n_vert][2],
+ * (qx, qy) in 1/Angstrom, n_vert >= 2): n_per_seg points per segment starting at its first vertex,
+ * then the last vertex, so n_pts = (n_vert - 1) n_per_seg + 1.  Each point is sampled bilinearly at
+ * the fractional pixel (qx lx + nqx/2, qy ly + nqy/2) of the centred map; pixels outside the map
+ * count as zero.
+ *   S    dev [n_e][nqy][nqx] float (tacaw_spectrum_finalize output)
+ *   out  dev [n_e][n_pts] float */
+int tacaw_path_cut(tacaw_ctx* ctx, double lx, double ly, int32_t nqx, int32_t nqy, int32_t n_e,
+                   const float* S, int32_t n_vert, const double* vertices, int32_t n_per_seg,
+                   float* out, void* stream);
+
+/* ----------------------------------------------------------------------------------------------
  * FFT schedule autotuning (the kernels' radix plan, lanes per line and columns per LDS tile).
  * Times every compiled variant of the slice-step kernels for grid n (nx = ny = n) on a scratch batch
  * of `n_waves` waves with HIP events, keeps the fastest per (n, pass) in the context and, when

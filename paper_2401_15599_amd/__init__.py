@@ -87,6 +87,11 @@ _SIGS = {
                                 ctypes.c_int),
     "tacaw_autocorr_spectrum_backward": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P,
                                           _P, _P, _P], ctypes.c_int),
+    "tacaw_energy_integrals": ([_P, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P, _P], ctypes.c_int),
+    "tacaw_qep_pattern": ([_P, _I, _I, _I, _I, _P, _I, _I, _I, _I, _I, _P, _P], ctypes.c_int),
+    "tacaw_relative_difference": ([_P, _I, _I, _P, _P, _P, _P], ctypes.c_int),
+    "tacaw_path_cut": ([_P, ctypes.c_double, ctypes.c_double, _I, _I, _I, _P, _I,
+                        ctypes.POINTER(ctypes.c_double), _I, _P, _P], ctypes.c_int),
     "tacaw_autotune": ([_P, _I, _I, ctypes.c_char_p, _P], ctypes.c_int),
     "tacaw_load_tuning": ([_P, ctypes.c_char_p], ctypes.c_int),
     "tacaw_describe_schedule": ([_P, _I], ctypes.c_char_p),
@@ -334,6 +339,38 @@ def tacaw_autocorr_spectrum_backward(ctx, exit, opts, S, norm, grad_S, grad_exit
     _check(_lib.tacaw_autocorr_spectrum_backward(ctx.handle, nx, ny, T, Pn, _ptr(exit),
                                                  ctypes.byref(o), _ptr(S), _ptr(norm),
                                                  _ptr(grad_S), _ptr(grad_exit), _stream(stream)))
+
+
+def tacaw_energy_integrals(ctx, P_acc, opts, c_tilde=None, c=None, stream=None):
+    _, ny, nx = P_acc.shape
+    o = opts.c()
+    _check(_lib.tacaw_energy_integrals(ctx.handle, nx, ny, _ptr(P_acc), ctypes.byref(o),
+                                       _ptr(c_tilde), _ptr(c), _stream(stream)))
+
+
+def tacaw_qep_pattern(ctx, exit, t0, t_stride, t_count, out, stream=None):
+    T, Pn, ny, nx = exit.shape
+    nqy, nqx = out.shape
+    _check(_lib.tacaw_qep_pattern(ctx.handle, nx, ny, T, Pn, _ptr(exit), t0, t_stride, t_count,
+                                  nqx, nqy, _ptr(out), _stream(stream)))
+
+
+def tacaw_relative_difference(ctx, A, B, out_row, stream=None):
+    nqy, nqx = A.shape
+    if tuple(B.shape) != (nqy, nqx) or out_row.numel() != nqx:
+        raise TacawError("maps and profile must share the crop")
+    _check(_lib.tacaw_relative_difference(ctx.handle, nqx, nqy, _ptr(A), _ptr(B), _ptr(out_row),
+                                          _stream(stream)))
+
+
+def tacaw_path_cut(ctx, lx, ly, S, vertices, n_per_seg, out, stream=None):
+    n_e, nqy, nqx = S.shape
+    arr, vp = _dbl(np.asarray(vertices, dtype=np.float64).reshape(-1, 2))
+    n_vert = arr.shape[0]
+    if out.shape[0] != n_e or out.shape[1] != (n_vert - 1) * n_per_seg + 1:
+        raise TacawError("out must be [n_e][(n_vert - 1) * n_per_seg + 1]")
+    _check(_lib.tacaw_path_cut(ctx.handle, float(lx), float(ly), nqx, nqy, n_e, _ptr(S), n_vert,
+                               vp, n_per_seg, _ptr(out), _stream(stream)))
 
 
 def tacaw_autotune(ctx, n, n_waves, cache_path=None, stream=None):

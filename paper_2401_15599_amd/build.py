@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libtacaw.so")
 HOSTCHECK = os.path.join(HERE, "fft_host_check")
 ARCH = os.environ.get("TACAW_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "ms_kernels.hip", "pot_kernels.hip", "spec_kernels.hip"]
+SOURCES = ["api.cpp", "ms_kernels.hip", "pot_kernels.hip", "spec_kernels.hip", "analysis_kernels.hip"]
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1217,6 +1217,98 @@ int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int
 }
 
 // ------------------------------------------------------------------------------------------------
+// analysis outputs
+static void validate_crop(int nx, int ny, int nqx, int nqy) {
+  if (nx < 1 || ny < 1 || (long)nx * ny > (1L << 30)) fail(TACAW_E_ARG, "bad grid");
+  if (nqx < 1 || nqx > nx || nqy < 1 || nqy > ny) fail(TACAW_E_ARG, "output crop outside the q grid");
+}
+
+int tacaw_energy_integrals(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* P_acc,
+                           const tacaw_spectrum_opts* opts, float* c_tilde, float* c,
+                           void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_opts(opts, nx, ny);
+    validate_crop(nx, ny, opts->nqx_out, opts->nqy_out);
+    if (!pow2_in(opts->n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
+    if (!P_acc || (!c_tilde && !c)) fail(TACAW_E_ARG, "null buffers");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> kd = kubo_dft_order(opts->n_e, opts->dt_fs, opts->temperature_k);
+    std::vector<float> kf(kd.begin(), kd.end());
+    const float* K = upload_vec(ctx, kf, st, "kubo");
+    const long nq = (long)nx * ny;
+    const int n_part = 512;
+    double* sums = (double*)workspace(ctx, "an_sums", 2 * nq * sizeof(double));
+    double* part = (double*)workspace(ctx, "an_partial", (n_part + 1) * sizeof(double));
+    hip_check(launch_energy_sums(P_acc, K, opts->n_e, nq, sums, sums + nq, st), "energy sums");
+    if (c_tilde)
+      hip_check(launch_norm_crop(sums, nq, nx, ny, opts->nqx_out, opts->nqy_out, part, n_part,
+                                 c_tilde, st), "pattern");
+    if (c)
+      hip_check(launch_norm_crop(sums + nq, nq, nx, ny, opts->nqx_out, opts->nqy_out, part, n_part,
+                                 c, st), "pattern");
+  });
+}
+
+int tacaw_qep_pattern(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
+                      const tacaw_c64* exit, int32_t t0, int32_t t_stride, int32_t t_count,
+                      int32_t nqx_out, int32_t nqy_out, float* out, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_crop(nx, ny, nqx_out, nqy_out);
+    if (n_snap < 1 || n_pos < 1 || !exit || !out) fail(TACAW_E_ARG, "bad exit stack or output");
+    if (t0 < 0 || t_stride < 1 || t_count < 1 || (long)t0 + (long)(t_count - 1) * t_stride >= n_snap)
+      fail(TACAW_E_ARG, "snapshot selection outside the stack");
+    hipStream_t st = (hipStream_t)stream;
+    const long nq = (long)nx * ny;
+    const int n_part = 512;
+    double* sums = (double*)workspace(ctx, "an_sums", 2 * nq * sizeof(double));
+    double* part = (double*)workspace(ctx, "an_partial", (n_part + 1) * sizeof(double));
+    hip_check(launch_snapshot_sums((const float2*)exit, n_pos, nq, t0, t_stride, t_count, sums, st),
+              "snapshot sums");
+    hip_check(launch_norm_crop(sums, nq, nx, ny, nqx_out, nqy_out, part, n_part, out, st), "pattern");
+  });
+}
+
+int tacaw_relative_difference(tacaw_ctx* ctx, int32_t nqx, int32_t nqy, const float* A,
+                              const float* B, float* out_row, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    if (nqx < 1 || nqy < 1 || !A || !B || !out_row) fail(TACAW_E_ARG, "bad maps or output");
+    hip_check(launch_rel_diff_row(A, B, nqx, nqy, out_row, (hipStream_t)stream), "profile");
+  });
+}
+
+int tacaw_path_cut(tacaw_ctx* ctx, double lx, double ly, int32_t nqx, int32_t nqy, int32_t n_e,
+                   const float* S, int32_t n_vert, const double* vertices, int32_t n_per_seg,
+                   float* out, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    if (!(lx > 0) || !(ly > 0)) fail(TACAW_E_ARG, "cell lengths must be positive");
+    if (nqx < 1 || nqy < 1 || n_e < 1 || !S || !out) fail(TACAW_E_ARG, "bad spectrum or output");
+    if (n_vert < 2 || !vertices || n_per_seg < 1) fail(TACAW_E_ARG, "need >= 2 vertices and >= 1 point per segment");
+    for (int i = 0; i < 2 * n_vert; ++i)
+      if (!std::isfinite(vertices[i])) fail(TACAW_E_ARG, "vertices must be finite");
+    // points along the polyline (n_per_seg per segment from its first vertex, then the last
+    // vertex) as fractional pixel positions of the centred map: q l + nq / 2
+    std::vector<double2> uv;
+    auto push = [&](double qx, double qy) {
+      uv.push_back(make_double2(qx * lx + (double)(nqx / 2), qy * ly + (double)(nqy / 2)));
+    };
+    for (int sgm = 0; sgm + 1 < n_vert; ++sgm)
+      for (int j = 0; j < n_per_seg; ++j) {
+        const double f = (double)j / n_per_seg;
+        push(vertices[2 * sgm] + f * (vertices[2 * sgm + 2] - vertices[2 * sgm]),
+             vertices[2 * sgm + 1] + f * (vertices[2 * sgm + 3] - vertices[2 * sgm + 1]));
+      }
+    push(vertices[2 * n_vert - 2], vertices[2 * n_vert - 1]);
+    hipStream_t st = (hipStream_t)stream;
+    const double2* d_uv = upload_vec(ctx, uv, st, "path");
+    hip_check(launch_path_cut(S, n_e, nqx, nqy, d_uv, (int)uv.size(), out, st), "path cut");
+  });
+}
+
+// ------------------------------------------------------------------------------------------------
 // timing instrumentation
 int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable) {
   return guarded([&] {

@@ -163,6 +163,19 @@ struct FinArgs {
   int n_e, nx, ny, nqx, nqy, n_part;
 };
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
+
+// analysis outputs (patterns, line profiles, dispersion cuts)
+hipError_t launch_energy_sums(const float* P, const float* K, int n_e, long nq, double* sp,
+                              double* skp, hipStream_t st);
+hipError_t launch_snapshot_sums(const float2* exit, int n_pos, long nq, int t0, int ts, int count,
+                                double* s, hipStream_t st);
+// x / (fixed-order total of x over nq), centred and cropped; partial: n_part + 1 doubles
+hipError_t launch_norm_crop(const double* x, long nq, int nx, int ny, int nqx, int nqy,
+                            double* partial, int n_part, float* out, hipStream_t st);
+hipError_t launch_rel_diff_row(const float* A, const float* B, int nqx, int nqy, float* out,
+                               hipStream_t st);
+hipError_t launch_path_cut(const float* S, int n_e, int nqx, int nqy, const double2* uv, int n_pts,
+                           float* out, hipStream_t st);
 struct SpecBwdArgs {
   const float2* exit; const float* S; const double* norm; const float* gS; const float* K;
   float2* gexit; double* partial;
