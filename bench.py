@@ -53,6 +53,8 @@ def parse():
                         "the workload (8 snapshots) and a 1 GiB device copy as HBM calibration")
     p.add_argument("--odd-grids-only", action="store_true",
                    help="run only the 560^2 and 1000^2 lines (for kernel traces of their passes)")
+    p.add_argument("--large-only", action="store_true",
+                   help="run only the large configuration at full size (1024^2, 2048 snapshots)")
     return p.parse_args()
 
 
@@ -297,6 +299,64 @@ def odd_grid_leg(tw):
     return out
 
 
+def large_run(tw, chunk=64, keep=False):
+    """The large configuration at full size: B/N-like hexagonal crystal of 40 x 40 x 50 cells
+    (640,000 atoms), 1024^2 grid, 100 slices of 3.33 A, 60 keV plane wave, 2048 snapshots at 2 fs
+    (trajectory seed 5001), S(q, w) with 1024 energy bins and hop 512 (3 segments).  Its potentials
+    (819 GB) cannot all be resident, so the snapshots stream through in chunks: potentials of a
+    chunk, then the chunk's batched multislice into the resident exit stack (17 GB); the spectrum
+    follows from the whole stack.  Returns timings (and, with keep, the device buffers)."""
+    import torch
+    from workloads.configs import CONFIGS, make_workload
+    from workloads.trajectory import harmonic_trajectory
+    cfg = CONFIGS["c5"]
+    ctx = tw.Context(0)
+    w = make_workload(cfg, generate=False, name="large-1024")
+    T, S = w.n_snap, w.n_slices
+    t_gen = time.perf_counter()
+    xyz = harmonic_trajectory(w.extra["structure"], T, w.dt_fs, w.seed, omega_a_mev=cfg["omega_a"],
+                              omega_o_mev=cfg["omega_o"], device="cuda:0")
+    species = torch.from_numpy(w.species).to("cuda:0")
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    sp, bm = tw.specimen_from(w), tw.beam_from(w)
+    ex = torch.empty((T, 1, w.ny, w.nx), dtype=torch.complex64, device="cuda:0")
+    V = torch.empty((chunk, S, w.ny, w.nx), dtype=torch.float32, device="cuda:0")
+    t_pot = t_ms = 0.0
+    for t0 in range(0, T, chunk):
+        n = min(chunk, T - t0)
+        a = time.perf_counter()
+        tw.tacaw_build_potentials(ctx, sp, xyz[t0:t0 + n], species, w.ff, V[:n])
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        tw.tacaw_multislice(ctx, [tw.MsJob(sp, bm, V[:n], ex[t0:t0 + n])], mode=tw.MODE_BATCHED)
+        torch.cuda.synchronize()
+        t_pot += b - a
+        t_ms += time.perf_counter() - b
+        if (t0 // chunk) % 8 == 7:
+            log(f"[large] {t0 + n}/{T} snapshots: potentials {t_pot:.1f} s, multislice {t_ms:.1f} s")
+    opts = tw.SpectrumOpts(w.dt_fs, w.temperature_k, w.n_e, w.hop, w.nx, w.ny)
+    Pacc = torch.empty((w.n_e, w.ny, w.nx), dtype=torch.float32, device="cuda:0")
+    Sq = torch.empty_like(Pacc)
+    norm = torch.empty((1,), dtype=torch.float64, device="cuda:0")
+    a = time.perf_counter()
+    tw.tacaw_periodogram(ctx, ex, w.n_e, w.hop, Pacc)
+    tw.tacaw_spectrum_finalize(ctx, Pacc, opts, Sq, norm)
+    torch.cuda.synchronize()
+    t_sp = time.perf_counter() - a
+    steps = T * S
+    out = dict(workload="B/N-like 40x40x50 cells (640,000 atoms), 1024^2, 100 slices, 60 keV plane "
+                        "wave, 2048 snapshots streamed in chunks of %d, S(q,w) 1024 bins hop 512" % chunk,
+               trajectory_s=t_gen, potentials_s=t_pot, multislice_s=t_ms, spectrum_s=t_sp,
+               slice_steps=steps, multislice_slice_steps_per_s=steps / t_ms,
+               total_s=t_gen + t_pot + t_ms + t_sp,
+               exit_stack_GB=ex.numel() * 8 / 1e9)
+    if keep:
+        out["tensors"] = dict(xyz=xyz, V=V, exit=ex, P=Pacc, S=Sq, norm=norm, w=w, ctx=ctx,
+                              last_t0=((T - 1) // chunk) * chunk)
+    return out
+
+
 def structure_factor_work(ws):
     """Complex multiply-adds the structure-factor contraction needs per step: for every map, the
     band-limited k points of the computed half plane (ky >= 0, the rest is the conjugate
@@ -403,6 +463,10 @@ def main():
         import paper_2401_15599_amd as tw
         print(json.dumps({"odd_grids": odd_grid_leg(tw)}))
         return
+    if args.large_only:
+        import paper_2401_15599_amd as tw
+        print(json.dumps({"large": large_run(tw)}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note only)"}))
@@ -491,6 +555,9 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] odd-length grid legs (560^2, 1000^2)")
         extra["odd_grids"] = odd_grid_leg(tw)
+        torch.cuda.empty_cache()
+        log("[bench] large configuration at full size (1024^2, 2048 snapshots, streamed)")
+        extra["large_1024"] = large_run(tw)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline (host cores)")
