@@ -43,7 +43,7 @@ typedef enum {
   TACAW_E_SIZE = -2,  /* a size outside what the kernels support (grid, segment length, species) */
   TACAW_E_HIP = -3,   /* a HIP runtime call failed; message from tacaw_last_error() */
   TACAW_E_NOMEM = -4, /* workspace allocation failed */
-  TACAW_E_STATE = -5  /* the context is unusable (wrong device, destroyed) */
+  TACAW_E_STATE = -5  /* an object is unusable (wrong device, destroyed, or a finished stream) */
 } tacaw_status;
 
 typedef struct tacaw_ctx tacaw_ctx;
@@ -222,6 +222,37 @@ typedef struct {
 int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
                       const tacaw_c64* exit, int32_t n_e, int32_t hop, float* P_acc,
                       int32_t accumulate, void* stream);
+
+/* The same periodogram over a sub-range of probe positions, pos0 .. pos0 + n_pos_used - 1, of an
+ * exit stack [n_snap][n_pos][ny][nx]: one spectrum per probe position of a scan (n_pos_used = 1),
+ * or positions accumulated chunk by chunk from one resident stack (accumulate = 1).
+ * Errors: as tacaw_periodogram, TACAW_E_ARG for a position range outside the stack. */
+int tacaw_periodogram_positions(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap,
+                                int32_t n_pos, const tacaw_c64* exit, int32_t pos0,
+                                int32_t n_pos_used, int32_t n_e, int32_t hop, float* P_acc,
+                                int32_t accumulate, void* stream);
+
+/* Streamed segment periodograms for trajectories too long to keep every exit wave (Sec. II, the
+ * averaging over segments of one long trajectory): exit waves arrive chunk by chunk in snapshot
+ * order; the object keeps only the snapshots a not-yet-complete segment still needs (a window
+ * of at most n_e + the largest chunk snapshots, in library-owned device memory), and adds each
+ * segment's |Phi_g|^2 to P_acc as soon as its last snapshot has arrived.  Segments start at
+ * multiples of hop (hop > n_e leaves gaps, like tacaw_periodogram).  finish scales P_acc by 1/G,
+ * so that it equals tacaw_periodogram of the whole stack with G complete segments.
+ *   create   P_acc dev [n_e][ny][nx] float, owned by the caller, written by push and finish
+ *   push     exit dev [n_snap][n_pos][ny][nx], the next n_snap snapshots (copied; the caller may
+ *            reuse its buffer once the stream has passed the copy)
+ *   finish   n_segments (host out, may be NULL): G; no further push
+ *   window   capacity and held snapshots of the window (host out, may be NULL)
+ * Errors: TACAW_E_ARG, TACAW_E_SIZE (grid, n_e, q tile as tacaw_periodogram), TACAW_E_NOMEM,
+ * TACAW_E_STATE (push or finish after finish; finish before a complete segment), TACAW_E_HIP. */
+typedef struct tacaw_segstream tacaw_segstream;
+int tacaw_segstream_create(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_pos, int32_t n_e,
+                           int32_t hop, float* P_acc, tacaw_segstream** out);
+int tacaw_segstream_push(tacaw_segstream* s, int32_t n_snap, const tacaw_c64* exit, void* stream);
+int tacaw_segstream_finish(tacaw_segstream* s, int32_t* n_segments, void* stream);
+int tacaw_segstream_window(const tacaw_segstream* s, int32_t* capacity, int32_t* held);
+void tacaw_segstream_destroy(tacaw_segstream* s);
 
 /* Kubo correction, normalisation, energy shift and q crop of an accumulated periodogram.
  *   S     dev out [n_e][nqy_out][nqx_out] float

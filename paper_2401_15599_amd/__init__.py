@@ -82,6 +82,13 @@ _SIGS = {
     "tacaw_multislice_adjoint": ([_P, _I, ctypes.POINTER(_Job), _I, ctypes.POINTER(_P),
                                   ctypes.POINTER(_P), _P], ctypes.c_int),
     "tacaw_periodogram": ([_P, _I, _I, _I, _I, _P, _I, _I, _P, _I, _P], ctypes.c_int),
+    "tacaw_periodogram_positions": ([_P, _I, _I, _I, _I, _P, _I, _I, _I, _I, _P, _I, _P],
+                                    ctypes.c_int),
+    "tacaw_segstream_create": ([_P, _I, _I, _I, _I, _I, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "tacaw_segstream_push": ([_P, _I, _P, _P], ctypes.c_int),
+    "tacaw_segstream_finish": ([_P, ctypes.POINTER(_I), _P], ctypes.c_int),
+    "tacaw_segstream_window": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], ctypes.c_int),
+    "tacaw_segstream_destroy": ([_P], None),
     "tacaw_spectrum_finalize": ([_P, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P, _P], ctypes.c_int),
     "tacaw_autocorr_spectrum": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P, _P],
                                 ctypes.c_int),
@@ -317,6 +324,43 @@ def tacaw_periodogram(ctx, exit, n_e, hop, P_acc, accumulate=False, stream=None)
     T, Pn, ny, nx = exit.shape
     _check(_lib.tacaw_periodogram(ctx.handle, nx, ny, T, Pn, _ptr(exit), n_e, hop, _ptr(P_acc),
                                   1 if accumulate else 0, _stream(stream)))
+
+
+def tacaw_periodogram_positions(ctx, exit, pos0, n_pos_used, n_e, hop, P_acc, accumulate=False,
+                                stream=None):
+    T, Pn, ny, nx = exit.shape
+    _check(_lib.tacaw_periodogram_positions(ctx.handle, nx, ny, T, Pn, _ptr(exit), pos0, n_pos_used,
+                                            n_e, hop, _ptr(P_acc), 1 if accumulate else 0,
+                                            _stream(stream)))
+
+
+class SegStream:
+    """Streamed segment periodograms (tacaw_segstream_*): push exit-wave chunks [n][n_pos][ny][nx]
+    in snapshot order, then finish() -> number of segments; P_acc then holds the periodogram."""
+
+    def __init__(self, ctx, nx, ny, n_pos, n_e, hop, P_acc):
+        h = _P()
+        _check(_lib.tacaw_segstream_create(ctx.handle, nx, ny, n_pos, n_e, hop, _ptr(P_acc),
+                                           ctypes.byref(h)))
+        self.handle, self.P = h, P_acc
+
+    def push(self, exit, stream=None):
+        _check(_lib.tacaw_segstream_push(self.handle, exit.shape[0], _ptr(exit), _stream(stream)))
+
+    def finish(self, stream=None):
+        g = _I(0)
+        _check(_lib.tacaw_segstream_finish(self.handle, ctypes.byref(g), _stream(stream)))
+        return g.value
+
+    def window(self):
+        cap, held = _I(0), _I(0)
+        _check(_lib.tacaw_segstream_window(self.handle, ctypes.byref(cap), ctypes.byref(held)))
+        return cap.value, held.value
+
+    def __del__(self, _destroy=_lib.tacaw_segstream_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
 
 
 def tacaw_spectrum_finalize(ctx, P_acc, opts, S, norm=None, stream=None):

@@ -129,6 +129,12 @@ __global__ __launch_bounds__(kAnThreads) void k_path_cut(const float* S, int n_e
   }
 }
 
+// x[i] *= s
+__global__ __launch_bounds__(kAnThreads) void k_scale(float* x, long n, float s) {
+  for (long i = blockIdx.x * (long)kAnThreads + threadIdx.x; i < n; i += (long)gridDim.x * kAnThreads)
+    x[i] *= s;
+}
+
 static int an_grid(long n) {
   const long b = (n + kAnThreads - 1) / kAnThreads;
   return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
@@ -167,6 +173,11 @@ hipError_t launch_path_cut(const float* S, int n_e, int nqx, int nqy, const doub
                            float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_path_cut, dim3(an_grid((long)n_e * n_pts)), dim3(kAnThreads), 0, st, S, n_e,
                      nqx, nqy, uv, n_pts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(float* x, long n, float s, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(an_grid(n)), dim3(kAnThreads), 0, st, x, n, s);
   return hipGetLastError();
 }
 

@@ -1105,6 +1105,36 @@ static void validate_spectrum(int nx, int ny, int n_snap, int n_pos, const tacaw
   if (n_e > n_snap) fail(TACAW_E_ARG, "segment longer than the trajectory");
 }
 
+int tacaw_periodogram_positions(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap,
+                                int32_t n_pos, const tacaw_c64* exit, int32_t pos0,
+                                int32_t n_pos_used, int32_t n_e, int32_t hop, float* P_acc,
+                                int32_t accumulate, void* stream) {
+  return guarded([&] {
+    use_device(ctx);
+    validate_spectrum(nx, ny, n_snap, n_pos, exit, n_e, hop);
+    if (!P_acc) fail(TACAW_E_ARG, "null P_acc");
+    if (pos0 < 0 || n_pos_used < 1 || (long)pos0 + n_pos_used > n_pos)
+      fail(TACAW_E_ARG, "position range outside the stack");
+    SpecArgs a{};
+    a.exit = (const float2*)exit;
+    a.P = P_acc;
+    a.T = n_snap;
+    a.Ps = n_pos;
+    a.p0 = pos0;
+    a.Pn = n_pos_used;
+    a.nq = nx * ny;
+    a.n_e = n_e;
+    a.hop = hop;
+    a.G = (n_snap - n_e) / hop + 1;
+    a.accumulate = accumulate ? 1 : 0;
+    const double bytes = 8.0 * nx * ny * (double)n_e * a.G * n_pos_used +
+                         (accumulate ? 8.0 : 4.0) * nx * ny * (double)n_e;
+    timed_launch(ctx, (hipStream_t)stream, "pgram", bytes, [&] {
+      hip_check(launch_periodogram(a, (hipStream_t)stream), "periodogram kernel");
+    });
+  });
+}
+
 int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,
                       const tacaw_c64* exit, int32_t n_e, int32_t hop, float* P_acc,
                       int32_t accumulate, void* stream) {
@@ -1116,6 +1146,8 @@ int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, in
     a.exit = (const float2*)exit;
     a.P = P_acc;
     a.T = n_snap;
+    a.Ps = n_pos;
+    a.p0 = 0;
     a.Pn = n_pos;
     a.nq = nx * ny;
     a.n_e = n_e;
@@ -1215,6 +1247,138 @@ int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int
     hip_check(launch_spectrum_backward(a, st), "spectrum backward");
   });
 }
+
+// ------------------------------------------------------------------------------------------------
+// streamed segment periodograms
+struct tacaw_segstream {
+  tacaw_ctx* ctx = nullptr;
+  int nx = 0, ny = 0, n_pos = 0, n_e = 0, hop = 0;
+  float* P = nullptr;            // caller's accumulator [n_e][ny][nx]
+  float2* win = nullptr;         // window of snapshots [cap][n_pos][nx ny] (library-owned)
+  long cap = 0;                  // window capacity (snapshots)
+  long w0 = 0;                   // trajectory index of window slot 0
+  long len = 0;                  // snapshots held
+  long pushed = 0;               // snapshots received so far
+  long done = 0;                 // segments accumulated
+  bool finished = false;
+  ~tacaw_segstream() {
+    if (win) {
+      (void)hipSetDevice(ctx->device);
+      (void)hipDeviceSynchronize();
+      (void)hipFree(win);
+    }
+  }
+};
+
+int tacaw_segstream_create(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_pos, int32_t n_e,
+                           int32_t hop, float* P_acc, tacaw_segstream** out) {
+  return guarded([&] {
+    use_device(ctx);
+    if (!out) fail(TACAW_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid_size_ok(nx) || !grid_size_ok(ny)) fail(TACAW_E_SIZE, "grid size");
+    if (n_pos < 1 || hop < 1 || !P_acc) fail(TACAW_E_ARG, "need n_pos >= 1, hop >= 1 and P_acc");
+    if (!pow2_in(n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
+    if (((long)nx * ny) % spectrum_q_tile(n_e) != 0)
+      fail(TACAW_E_SIZE, "nx * ny must be a multiple of " + std::to_string(spectrum_q_tile(n_e)));
+    auto s = std::make_unique<tacaw_segstream>();
+    s->ctx = ctx;
+    s->nx = nx;
+    s->ny = ny;
+    s->n_pos = n_pos;
+    s->n_e = n_e;
+    s->hop = hop;
+    s->P = P_acc;
+    *out = s.release();
+  });
+}
+
+int tacaw_segstream_push(tacaw_segstream* s, int32_t n_snap, const tacaw_c64* exit, void* stream) {
+  return guarded([&] {
+    if (!s) fail(TACAW_E_ARG, "null stream object");
+    use_device(s->ctx);
+    if (s->finished) fail(TACAW_E_STATE, "the stream was finished");
+    if (n_snap < 1 || !exit) fail(TACAW_E_ARG, "need n_snap >= 1 and exit waves");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t snap = (size_t)s->n_pos * s->nx * s->ny;   // complex values per snapshot
+    if (s->len + n_snap > s->cap) {
+      const long cap = std::max<long>({2 * s->cap, s->len + n_snap, (long)s->n_e + n_snap});
+      float2* nw = nullptr;
+      if (hipMalloc(&nw, (size_t)cap * snap * sizeof(float2)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(TACAW_E_NOMEM, "segment stream window of " + std::to_string(cap) + " snapshots");
+      }
+      if (s->len > 0)
+        hip_check(hipMemcpyAsync(nw, s->win, (size_t)s->len * snap * sizeof(float2),
+                                 hipMemcpyDeviceToDevice, st), "window copy");
+      if (s->win) {
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        hip_check(hipFree(s->win), "hipFree");
+      }
+      s->win = nw;
+      s->cap = cap;
+    }
+    hip_check(hipMemcpyAsync(s->win + (size_t)s->len * snap, exit, (size_t)n_snap * snap * sizeof(float2),
+                             hipMemcpyDeviceToDevice, st), "window append");
+    s->len += n_snap;
+    s->pushed += n_snap;
+    // every segment whose snapshots have all arrived: its periodogram, added to P
+    while (s->done * s->hop + s->n_e <= s->pushed) {
+      const long off = s->done * s->hop - s->w0;
+      SpecArgs a{};
+      a.exit = s->win + (size_t)off * snap;
+      a.P = s->P;
+      a.T = s->n_e;
+      a.Ps = s->n_pos;
+      a.p0 = 0;
+      a.Pn = s->n_pos;
+      a.nq = s->nx * s->ny;
+      a.n_e = s->n_e;
+      a.hop = s->n_e;
+      a.G = 1;
+      a.accumulate = s->done > 0 ? 1 : 0;
+      hip_check(launch_periodogram(a, st), "periodogram kernel");
+      ++s->done;
+    }
+    // drop the snapshots before the next segment's start (moved down in pieces that do not
+    // overlap their destination)
+    const long keep_from = s->done * s->hop;
+    const long shift = std::min(std::max(0L, keep_from - s->w0), s->len);
+    if (shift > 0) {
+      for (long o = 0; o < s->len - shift; o += shift) {
+        const long m = std::min(shift, s->len - shift - o);
+        hip_check(hipMemcpyAsync(s->win + (size_t)o * snap, s->win + (size_t)(shift + o) * snap,
+                                 (size_t)m * snap * sizeof(float2), hipMemcpyDeviceToDevice, st),
+                  "window shift");
+      }
+      s->w0 += shift;
+      s->len -= shift;
+    }
+  });
+}
+
+int tacaw_segstream_finish(tacaw_segstream* s, int32_t* n_segments, void* stream) {
+  return guarded([&] {
+    if (!s) fail(TACAW_E_ARG, "null stream object");
+    use_device(s->ctx);
+    if (s->finished) fail(TACAW_E_STATE, "the stream was finished");
+    if (s->done < 1) fail(TACAW_E_STATE, "no complete segment was pushed");
+    hip_check(launch_scale(s->P, (long)s->n_e * s->nx * s->ny, (float)(1.0 / (double)s->done),
+                           (hipStream_t)stream), "scale");
+    s->finished = true;
+    if (n_segments) *n_segments = (int32_t)s->done;
+  });
+}
+
+int tacaw_segstream_window(const tacaw_segstream* s, int32_t* capacity, int32_t* held) {
+  return guarded([&] {
+    if (!s) fail(TACAW_E_ARG, "null stream object");
+    if (capacity) *capacity = (int32_t)s->cap;
+    if (held) *held = (int32_t)s->len;
+  });
+}
+
+void tacaw_segstream_destroy(tacaw_segstream* s) { delete s; }
 
 // ------------------------------------------------------------------------------------------------
 // analysis outputs

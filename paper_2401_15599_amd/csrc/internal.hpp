@@ -152,9 +152,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
 // spectrum
 struct SpecArgs {
-  const float2* exit;      // [T][P][nq]
+  const float2* exit;      // [T][Ps][nq]; positions p0 .. p0 + Pn - 1 are used
   float* P;                // [n_e][nq]
   int T, Pn, nq, n_e, hop, G, accumulate, Qt;
+  int Ps, p0;              // positions per snapshot in memory, first position used
 };
 hipError_t launch_periodogram(const SpecArgs& a, hipStream_t st);
 struct FinArgs {
@@ -174,6 +175,7 @@ hipError_t launch_norm_crop(const double* x, long nq, int nx, int ny, int nqx, i
                             double* partial, int n_part, float* out, hipStream_t st);
 hipError_t launch_rel_diff_row(const float* A, const float* B, int nqx, int nqy, float* out,
                                hipStream_t st);
+hipError_t launch_scale(float* x, long n, float s, hipStream_t st);
 hipError_t launch_path_cut(const float* S, int n_e, int nqx, int nqy, const double2* uv, int n_pts,
                            float* out, hipStream_t st);
 struct SpecBwdArgs {

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void k_periodogram(SpecArgs a) {
         for (int idx = threadIdx.x; idx < N * QT; idx += kThreads) {
           const int qi = idx % QT, t = idx / QT;
           tile[qi * CS + lds_pad(t)] =
-              a.exit[((size_t)(g * a.hop + t) * a.Pn + p) * a.nq + q0 + qi];
+              a.exit[((size_t)(g * a.hop + t) * a.Ps + a.p0 + p) * a.nq + q0 + qi];
         }
         __syncthreads();
 #pragma unroll

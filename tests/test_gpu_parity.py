@@ -392,6 +392,54 @@ def test_spectrum_position_chunks_accumulate():
     check(P.cpu().numpy(), ref, 1e-5)
 
 
+def test_per_position_periodograms():
+    """One periodogram per probe position of a stack (position sub-ranges of the same buffer)
+    matches the oracle on that position alone, and the positions accumulated one at a time give
+    the periodogram of all of them."""
+    rng = np.random.default_rng(7)
+    ex = (rng.normal(size=(40, 5, 16, 32)) + 1j * rng.normal(size=(40, 5, 16, 32))).astype(np.complex64)
+    g = _gpu(ex)
+    cx = ctx()
+    P = torch.empty((16, 16, 32), dtype=torch.float32, device=DEV)
+    for p in range(5):
+        tw.tacaw_periodogram_positions(cx, g, p, 1, 16, 8, P)
+        check(P.cpu().numpy(), o_sp.segment_periodogram(ex[:, p:p + 1].astype(np.complex128), 16, 8),
+              1e-5)
+    for p in range(5):
+        tw.tacaw_periodogram_positions(cx, g, p, 1, 16, 8, P, accumulate=p > 0)
+    check(P.cpu().numpy(), o_sp.segment_periodogram(ex.astype(np.complex128), 16, 8), 1e-5)
+    tw.tacaw_periodogram_positions(cx, g, 1, 3, 16, 8, P)
+    check(P.cpu().numpy(), o_sp.segment_periodogram(ex[:, 1:4].astype(np.complex128), 16, 8), 1e-5)
+    with pytest.raises(tw.TacawError, match="position range"):
+        tw.tacaw_periodogram_positions(cx, g, 3, 3, 16, 8, P)
+
+
+@pytest.mark.parametrize("n_e,hop,chunks", [(16, 6, (5, 13, 1, 20, 31)), (16, 20, (7, 7, 7, 49)),
+                                             (32, 32, (64,)), (16, 16, (1,) * 70)])
+def test_streamed_segments_equal_the_stack_periodogram(n_e, hop, chunks):
+    """Pushing the exit waves chunk by chunk gives the periodogram of the whole stack, with a
+    window of at most n_e + the largest chunk snapshots."""
+    rng = np.random.default_rng(n_e + hop)
+    T = sum(chunks)
+    ex = (rng.normal(size=(T, 2, 16, 32)) + 1j * rng.normal(size=(T, 2, 16, 32))).astype(np.complex64)
+    g = _gpu(ex)
+    cx = ctx()
+    P = torch.empty((n_e, 16, 32), dtype=torch.float32, device=DEV)
+    st = tw.SegStream(cx, 32, 16, 2, n_e, hop, P)
+    t = 0
+    for c in chunks:
+        buf = g[t:t + c].clone()          # a fresh buffer per chunk, as a multislice would give
+        st.push(buf)
+        t += c
+        cap, held = st.window()
+        assert held <= n_e + max(chunks) and cap <= 2 * (n_e + max(chunks))
+    G = st.finish()
+    assert G == (T - n_e) // hop + 1
+    check(P.cpu().numpy(), o_sp.segment_periodogram(ex.astype(np.complex128), n_e, hop), 1e-5)
+    with pytest.raises(tw.TacawError, match="finished"):
+        st.push(g[:1].clone())
+
+
 # ------------------------------------------------------------------------------------------------
 # end to end (configs[0])
 
