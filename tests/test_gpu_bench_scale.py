@@ -60,3 +60,41 @@ def test_bench_configuration_sampled_waves_match_oracle():
         phi_ref = o_ms.exit_waves(V_ref, w, w)[0, 0]
         e = rel_l2(exits[j][t, p].cpu().numpy(), phi_ref)
         assert e <= 1e-4, f"{w.name} snapshot {t} position {p}: exit wave rel-L2 {e:.3e}"
+
+
+def test_all_three_grid_classes_in_one_uneven_call():
+    """The uneven batch at its full specimen set: the 24 specimens of the 128^2, 256^2 and 512^2
+    classes (10..80 slices each) in one batched call with 8 probe positions and 2 snapshots each.
+    One wave per class is recomputed by the oracle (a thick 128^2 specimen, a mid 256^2 one and a
+    thin 512^2 one); every wave is checked for finite values and 0.5 < sum |phi|^2 <= 1."""
+    cfgs = c3_specimens()
+    assert len(cfgs) == 24 and {c["n"] for c in cfgs} == {(128, 128), (256, 256), (512, 512)}
+    ws = [make_workload(c, n_snap=T, name=f"c3-{c['n'][0]}-S{c['n_slices']}") for c in cfgs]
+    ctx = tw.context(0)
+    Vs, exits, jobs = [], [], []
+    for w in ws:
+        sp = tw.specimen_from(w)
+        V = torch.empty((T, w.n_slices, w.ny, w.nx), dtype=torch.float32, device=DEV)
+        tw.tacaw_build_potentials(ctx, sp, torch.from_numpy(w.positions).to(DEV),
+                                  torch.from_numpy(w.species).to(DEV), w.ff, V)
+        ex = torch.empty((T, POS, w.ny, w.nx), dtype=torch.complex64, device=DEV)
+        ex.fill_(float("nan"))
+        b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[:POS])
+        Vs.append(V)
+        exits.append(ex)
+        jobs.append(tw.MsJob(sp, b, V, ex))
+    tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
+    torch.cuda.synchronize()
+    for w, ex in zip(ws, exits):
+        e = ex.cpu().numpy()
+        assert np.all(np.isfinite(e.view(np.float32))), w.name
+        norm = np.sum(np.abs(e) ** 2, axis=(2, 3))
+        assert np.all(norm > 0.5) and np.all(norm <= 1.0 + 1e-4), (w.name, norm.min(), norm.max())
+    for n, S, t, p in ((128, 80, 1, 5), (256, 40, 0, 2), (512, 10, 1, 7)):
+        j = [k for k, w in enumerate(ws) if w.nx == n and w.n_slices == S][0]
+        w = ws[j]
+        Vt = Vs[j][t:t + 1].cpu().numpy().astype(np.float64)
+        w.probe_xy = w.probe_xy[p:p + 1]
+        phi_ref = o_ms.exit_waves(Vt, w, w)[0, 0]
+        e = rel_l2(exits[j][t, p].cpu().numpy(), phi_ref)
+        assert e <= 1e-4, f"{w.name} snapshot {t} position {p}: exit wave rel-L2 {e:.3e}"
