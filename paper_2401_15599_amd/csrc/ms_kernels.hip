@@ -29,8 +29,10 @@ template <class F> static bool with_plan(int n, int idx, F&& f) {
     case 256: if (idx == 1) f(P256b{}); else if (idx == 2) f(P256c{}); else f(P256a{}); return true;
     case 512: if (idx == 1) f(P512b{}); else f(P512a{}); return true;
     case 1024: if (idx == 1) f(P1024b{}); else f(P1024a{}); return true;
-    case 560: if (idx == 1) f(P560b{}); else f(P560a{}); return true;
-    case 1000: f(P1000a{}); return true;
+    case 560:
+      if (idx == 1) f(P560b{}); else if (idx == 2) f(P560c{}); else if (idx == 3) f(P560d{}); else f(P560a{});
+      return true;
+    case 1000: if (idx == 1) f(P1000b{}); else f(P1000a{}); return true;
     default: return false;
   }
 }
@@ -39,8 +41,8 @@ int n_plans(int n) {
   switch (n) {
     case 16: case 32: case 64: case 128: case 512: case 1024: return 2;
     case 256: return 3;
-    case 560: return 2;
-    case 1000: return 1;
+    case 560: return 4;
+    case 1000: return 2;
     default: return 0;
   }
 }
@@ -50,12 +52,13 @@ const char* plan_name(int n, int idx) {
                                 "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "256:L32:8x8x4",
                                 "256:L16:16x16", "256:L64:4x4x4x4", "512:L64:8x8x8",
                                 "512:L32:16x8x4", "1024:L64:16x16x4", "1024:L64:16x4x16",
-                                "560:L28:4x5x4x7", "560:L56:2x5x2x2x14", "1000:L50:4x5x5x10"};
+                                "560:L28:4x5x4x7", "560:L56:2x5x2x2x14", "560:L28:20x4x7",
+                                "560:L28:20x28", "1000:L50:4x5x5x10", "1000:L50:10x10x10"};
   int base = 0;
   switch (n) {
     case 16: base = 0; break; case 32: base = 2; break; case 64: base = 4; break;
     case 128: base = 6; break; case 256: base = 8; break; case 512: base = 11; break;
-    case 1024: base = 13; break; case 560: base = 15; break; case 1000: base = 17; break;
+    case 1024: base = 13; break; case 560: base = 15; break; case 1000: base = 19; break;
     default: return "?";
   }
   if (idx < 0 || idx >= n_plans(n)) return "?";

@@ -24,7 +24,10 @@ using P1024b = Plan<1024, 64, 16, 4, 16>;
 // then an in-place LDS stage of the remaining radix
 using P560a = Plan<560, 28, 4, 5, 4, 7>;     // E = 20, 2 lines per wavefront (lanes 56..63 idle)
 using P560b = Plan<560, 56, 2, 5, 2, 2, 14>; // E = 10, 1 line per wavefront (lanes 56..63 idle)
+using P560c = Plan<560, 28, 20, 4, 7>;       // E = 20: one exchange fewer than P560a
+using P560d = Plan<560, 28, 20, 28>;         // E = 20: one exchange, then an LDS radix-28 stage
 using P1000a = Plan<1000, 50, 4, 5, 5, 10>;  // E = 20, 1 line per wavefront (lanes 50..63 idle)
+using P1000b = Plan<1000, 50, 10, 10, 10>;   // E = 20, register stages only
 }  // namespace tacaw
 
 // X(name, plan) for every plan
@@ -36,5 +39,6 @@ using P1000a = Plan<1000, 50, 4, 5, 5, 10>;  // E = 20, 1 line per wavefront (la
   X("n256 L64 4x4x4x4", tacaw::P256c) X("n512 L64 8x8x8", tacaw::P512a)                          \
   X("n512 L32 16x8x4", tacaw::P512b) X("n1024 L64 16x16x4", tacaw::P1024a)                       \
   X("n1024 L64 16x4x16", tacaw::P1024b) X("n560 L28 4x5x4x7", tacaw::P560a)                        \
-  X("n560 L56 2x5x2x2x14", tacaw::P560b)                        \
-  X("n1000 L50 4x5x5x10", tacaw::P1000a)
+  X("n560 L56 2x5x2x2x14", tacaw::P560b) X("n560 L28 20x4x7", tacaw::P560c)                     \
+  X("n560 L28 20x28", tacaw::P560d)                                                              \
+  X("n1000 L50 4x5x5x10", tacaw::P1000a) X("n1000 L50 10x10x10", tacaw::P1000b)
