@@ -338,6 +338,24 @@ TACAW_HD void sincos_phase(float x, float* s, float* c) {
   *c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// exp(-2 pi i m U / 2^32) for signed index m.  The phase m U is exact in 32-bit fixed point (turns);
+// its nearest quarter turn q comes from integer rounding, the remainder r (|r| <= pi/4) is converted
+// to radians once, and sin r, cos r are Taylor polynomials (truncation below 2e-9; the remainder's
+// conversion costs at most 1e-7 rad), placed in the quadrant by swaps and signs.
+TACAW_HD float2 phase_factor(int m, unsigned U) {
+  const unsigned ph = (unsigned)m * U;
+  const unsigned q = (ph + 0x20000000u) >> 30;
+  const float r = (float)(int)(ph - (q << 30)) * 1.46291807926715968e-9f;   // 2 pi / 2^32
+  const float r2 = r * r;
+  const float sp = r + r * r2 * fmaf(r2, fmaf(r2, fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f),
+                                               1.0f / 120.0f), -1.0f / 6.0f);
+  const float cp = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f),
+                                                   -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
+  const float ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
+  const float s = (q & 2) ? -ss : ss, c = ((q + 1) & 2) ? -cc : cc;
+  return make_float2(c, -s);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Plans
 

@@ -127,8 +127,27 @@ static int check_sincos() {
   return ok ? 0 : 1;
 }
 
+// phase_factor against exp(-2 pi i (m U mod 2^32) / 2^32) in double: random fixed-point coordinates
+// and signed indices up to +-512, plus the phases nearest every quadrant and octant boundary
+static int check_phase_factor() {
+  double worst = 0;
+  auto probe = [&](int m, unsigned U) {
+    const float2 f = phase_factor(m, U);
+    const unsigned ph = (unsigned)m * U;
+    const double a = -2.0 * M_PI * (double)ph / 4294967296.0;
+    worst = std::max(worst, std::max(std::fabs(f.x - std::cos(a)), std::fabs(f.y - std::sin(a))));
+  };
+  std::mt19937 g(11);
+  for (int i = 0; i < 2000000; ++i) probe((int)(g() % 1024u) - 512, (unsigned)g());
+  for (unsigned b = 0; b < 8; ++b)
+    for (int d = -40; d <= 40; ++d) probe(1, b * 0x20000000u + (unsigned)d);
+  const bool ok = worst < 2.5e-7;
+  std::printf("%-28s max abs error %.2e  %s\n", "phase_factor", worst, ok ? "ok" : "FAIL");
+  return ok ? 0 : 1;
+}
+
 int main() {
-  int bad = check_sincos();
+  int bad = check_sincos() + check_phase_factor();
 #define TACAW_CHECK_PLAN(NAME, ...) bad += check<__VA_ARGS__>(NAME);
   TACAW_FOR_EACH_PLAN(TACAW_CHECK_PLAN)
   std::printf("%s\n", bad ? "FFT host check FAILED" : "FFT host check passed");

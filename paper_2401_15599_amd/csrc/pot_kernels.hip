@@ -113,15 +113,6 @@ __device__ __forceinline__ unsigned frac_fixed(float x, double len) {
   return (unsigned)(q & 0xffffffffLL);
 }
 
-// exp(-2 pi i m U / 2^32) for signed index m
-__device__ __forceinline__ float2 phase_factor(int m, unsigned U) {
-  unsigned ph = (unsigned)m * U;
-  float half_turns = (float)(int)ph * 4.656612873077393e-10f;   // * 2^-31
-  float s, c;
-  sincospif(half_turns, &s, &c);
-  return make_float2(c, -s);
-}
-
 __device__ __forceinline__ float form_factor(const float* f, float q2) {
   return f[0] / (q2 + f[1]) + f[2] / (q2 + f[3]) + f[4] / (q2 + f[5]) +
          f[6] * __expf(-f[7] * q2) + f[8] * __expf(-f[9] * q2) + f[10] * __expf(-f[11] * q2);
@@ -165,12 +156,20 @@ __global__ __launch_bounds__(256) void k_atom_phase(const float* xyz, const int*
 // generated once per workgroup in LDS.
 //   SPLIT = false: fp32 operands, four v_mfma_f32_32x32x2f32 per atom pair.
 //   SPLIT = true:  every phase component p is split as p = hi + lo with hi = fp16(p) (rounded
-//                  toward zero) and lo = fp16(p - hi); hi*hi + hi*lo + lo*hi are accumulated in fp32
+//                  toward zero) and lo = fp16(p - hi) (nearest); hi*hi + hi*lo + lo*hi accumulate in fp32
 //                  by v_mfma_f32_32x32x16_f16 (the dropped lo*lo term is below 2^-22 for unit
 //                  phases), twelve MFMAs per 16 atoms.
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __fp16 h2 __attribute__((ext_vector_type(2)));   // the packing builtin's type
+// the fp16 pair (x0 - hi[0], x1 - hi[1]) rounded to nearest, hi being the packed fp16 high parts
+// of x0 and x1: one mixed-precision fused multiply-add per half (x - hi is exact in fp32)
+__device__ __forceinline__ h2 split_lo(float x0, float x1, h2 hi) {
+  unsigned d;
+  asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(d) : "v"(x0), "v"(hi));
+  asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(d) : "v"(x1), "v"(hi));
+  return __builtin_bit_cast(h2, d);
+}
 constexpr int kSfChunk = 32;   // atoms per phase-table fill
 constexpr int kSfBatch = 256;  // atom records staged per LDS batch (the next batch is in flight)
 constexpr int kRowH = 40;      // halves per (component, k) row of a split table: 32 atoms + pad
@@ -340,8 +339,8 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
           }
           const h2 rh = __builtin_amdgcn_cvt_pkrtz(f[0].x, f[1].x);
           const h2 ih = __builtin_amdgcn_cvt_pkrtz(f[0].y, f[1].y);
-          const h2 rl = __builtin_amdgcn_cvt_pkrtz(f[0].x - (float)rh[0], f[1].x - (float)rh[1]);
-          const h2 il = __builtin_amdgcn_cvt_pkrtz(f[0].y - (float)ih[0], f[1].y - (float)ih[1]);
+          const h2 rl = split_lo(f[0].x, f[1].x, rh);
+          const h2 il = split_lo(f[0].y, f[1].y, ih);
           _Float16* dst = row + split_row(k0 + q);
           *reinterpret_cast<h2*>(dst) = rh;
           *reinterpret_cast<h2*>(dst + kTabH) = ih;

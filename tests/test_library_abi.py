@@ -52,6 +52,8 @@ def test_fft_plans_cpu_emulation():
     assert "FFT host check passed" in r.stdout
     # the odd-length plans (radices 4, 5, 7 and 10 with an in-place LDS last stage) are covered
     assert "n560" in r.stdout and "n1000" in r.stdout
+    # the structure factor's fixed-point phase factors
+    assert "phase_factor" in r.stdout
 
 
 def test_plan_counts_cover_the_supported_grids():
