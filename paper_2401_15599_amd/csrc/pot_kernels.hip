@@ -171,13 +171,18 @@ __device__ __forceinline__ h2 split_lo(float x0, float x1, h2 hi) {
   return __builtin_bit_cast(h2, d);
 }
 constexpr int kSfChunk = 32;   // atoms per phase-table fill
-constexpr int kSfBatch = 256;  // atom records staged per LDS batch (the next batch is in flight)
-constexpr int kRowH = 40;      // halves per (component, k) row of a split table: 32 atoms + pad
-// rows 8 apart would fall in the same LDS banks (8 x 80 bytes); every group of 8 rows starts a
-// further 64 bytes on, so that the generator's half-wave stores (16 atom pairs x 2 row groups) and
-// the operand reads (8 rows x 16 bytes per pass) are conflict-free
-__device__ __forceinline__ int split_row(int r) { return r * kRowH + (r >> 3) * 32; }
-constexpr int kTabH = kTile * kRowH + (kTile / 8) * 32;   // halves per (axis, component) table
+// atom records staged per LDS batch (the next batch is in flight in registers)
+template <bool SPLIT> constexpr int sf_batch() { return SPLIT ? 96 : 256; }
+// Split tables: a (component, k) row holds the 32 atoms of a chunk in four 16-byte granules (8 atoms
+// each).  Row r starts at 64 r bytes plus 64 bytes per preceding group of 8 rows, and its granules
+// are permuted by XOR with h(r).  With 64 banks of 4 bytes (16 lanes per 16-byte read) or 32 banks
+// (8 lanes per read), the operand reads (16 consecutive rows, one granule each) and the generator's
+// stores (16 atom pairs x 4 rows 8 apart) both fill distinct banks.
+__device__ __forceinline__ int row_h(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & ~r & 1); }
+__device__ __forceinline__ int split_at(int r, int granule) {   // halves from the table start
+  return 32 * r + 32 * (r >> 3) + 8 * (granule ^ row_h(r));
+}
+constexpr int kTabH = 32 * kTile + 32 * (kTile / 8);   // halves per (axis, component) table
 
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
@@ -187,7 +192,8 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
   __shared__ __attribute__((aligned(16))) char tables[SPLIT ? kBytesF16 : kBytesF32];
   float2 (*ex)[kTile + 1] = reinterpret_cast<float2 (*)[kTile + 1]>(tables);
   float2 (*ey)[kTile + 1] = reinterpret_cast<float2 (*)[kTile + 1]>(tables) + kSfChunk;
-  _Float16* tb = reinterpret_cast<_Float16*>(tables);   // [axis][component][split_row(k) + atom]
+  _Float16* tb = reinterpret_cast<_Float16*>(tables);   // [axis][component][split_at(k, atom / 8)]
+  constexpr int kSfBatch = sf_batch<SPLIT>();
   __shared__ AtomPhase batch[kSfBatch];   // phase records of up to kSfBatch atoms of one species
   __shared__ float ffs[kMaxSpecies * 12];
   // Hermitian mode (band limit on, ny >= 128): only storage rows [0, ny/2) are computed; row
@@ -234,9 +240,21 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
 
   const int lane = tid & 63, w = tid >> 6, wy = w >> 1, wx = w & 1;
   const int li = lane & 31, lk = lane >> 5;
-  v16f vr = {0}, vi = {0};
   const int* off = a.offsets + (size_t)t * (a.s_count * a.n_species + 1);
   const AtomPhase* R = (const AtomPhase*)a.arec + (size_t)(t - a.t0) * a.n_atoms;
+  // the species present in this slice; the sums of all but the last one pass through the output
+  // (no per-species accumulators in registers)
+  int zfirst = -1, zlast = -1;
+  for (int z = 0; z < a.n_species; ++z)
+    if (off[s * a.n_species + z + 1] > off[s * a.n_species + z]) {
+      if (zfirst < 0) zfirst = z;
+      zlast = z;
+    }
+  if (zlast < 0) {
+    for (int i = tid; i < TWe * THe; i += 256) put(n0 + i / TWe, m0 + i % TWe, make_float2(0.f, 0.f));
+    return;
+  }
+  const int tj = 32 * wx + li;
   for (int z = 0; z < a.n_species; ++z) {
     const int j0 = off[s * a.n_species + z], j1 = off[s * a.n_species + z + 1];
     if (j1 <= j0) continue;
@@ -246,7 +264,7 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
     const uint2* Rw = reinterpret_cast<const uint2*>(R);
     uint2* bw = reinterpret_cast<uint2*>(batch);
     uint2 nr0 = make_uint2(0u, 0u), nr1 = nr0, nr2 = nr0;
-    if (j0 + tid < j1) {
+    if (tid < kSfBatch && j0 + tid < j1) {
       nr0 = Rw[3 * (j0 + tid)];
       nr1 = Rw[3 * (j0 + tid) + 1];
       nr2 = Rw[3 * (j0 + tid) + 2];
@@ -256,14 +274,16 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
       const int bi = (c0 - j0) % kSfBatch;    // chunk offset in the staged batch
       __syncthreads();                        // previous chunk's tables (and batch) are consumed
       if (bi == 0) {
-        bw[3 * tid] = nr0;                    // this batch (loaded one batch ahead)
-        bw[3 * tid + 1] = nr1;
-        bw[3 * tid + 2] = nr2;
-        const int nb = c0 + kSfBatch + tid;   // prefetch the next batch of this species
-        if (nb < j1) {
-          nr0 = Rw[3 * nb];
-          nr1 = Rw[3 * nb + 1];
-          nr2 = Rw[3 * nb + 2];
+        if (tid < kSfBatch) {
+          bw[3 * tid] = nr0;                  // this batch (loaded one batch ahead)
+          bw[3 * tid + 1] = nr1;
+          bw[3 * tid + 2] = nr2;
+          const int nb = c0 + kSfBatch + tid; // prefetch the next batch of this species
+          if (nb < j1) {
+            nr0 = Rw[3 * nb];
+            nr1 = Rw[3 * nb + 1];
+            nr2 = Rw[3 * nb + 2];
+          }
         }
         __syncthreads();
       }
@@ -329,7 +349,7 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
         }
         // hi = fp16 of p rounded toward zero (packed for the atom pair), lo = fp16(p - hi); p - hi
         // is exact in fp32 and |lo| < one fp16 ulp of p
-        _Float16* row = tb + axis * 4 * kTabH + 2 * pair;
+        _Float16* row = tb + axis * 4 * kTabH + 2 * (pair & 3);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           if (wraps && q == qw) {
@@ -341,7 +361,7 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
           const h2 ih = __builtin_amdgcn_cvt_pkrtz(f[0].y, f[1].y);
           const h2 rl = split_lo(f[0].x, f[1].x, rh);
           const h2 il = split_lo(f[0].y, f[1].y, ih);
-          _Float16* dst = row + split_row(k0 + q);
+          _Float16* dst = row + split_at(k0 + q, pair >> 2);
           *reinterpret_cast<h2*>(dst) = rh;
           *reinterpret_cast<h2*>(dst + kTabH) = ih;
           *reinterpret_cast<h2*>(dst + 2 * kTabH) = rl;
@@ -362,18 +382,18 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
           ci = __builtin_amdgcn_mfma_f32_32x32x2f32(yv.y, xv.x, ci, 0, 0, 0);
         }
       } else {
-        const _Float16* ty = tb + 4 * kTabH + split_row(32 * wy + li);
-        const _Float16* tx = tb + split_row(32 * wx + li);
         for (int b = 0; 16 * b < na; ++b) {
-          const int kb = 16 * b + 8 * lk;
-          const v8h yrh = *reinterpret_cast<const v8h*>(ty + kb);
-          const v8h yih = *reinterpret_cast<const v8h*>(ty + kTabH + kb);
-          const v8h yrl = *reinterpret_cast<const v8h*>(ty + 2 * kTabH + kb);
-          const v8h yil = *reinterpret_cast<const v8h*>(ty + 3 * kTabH + kb);
-          const v8h xrh = *reinterpret_cast<const v8h*>(tx + kb);
-          const v8h xih = *reinterpret_cast<const v8h*>(tx + kTabH + kb);
-          const v8h xrl = *reinterpret_cast<const v8h*>(tx + 2 * kTabH + kb);
-          const v8h xil = *reinterpret_cast<const v8h*>(tx + 3 * kTabH + kb);
+          // atoms 16 b + 8 lk .. + 7 of rows 32 wy + li (y) and 32 wx + li (x)
+          const _Float16* ty = tb + 4 * kTabH + split_at(32 * wy + li, 2 * b + lk);
+          const _Float16* tx = tb + split_at(32 * wx + li, 2 * b + lk);
+          const v8h yrh = *reinterpret_cast<const v8h*>(ty);
+          const v8h yih = *reinterpret_cast<const v8h*>(ty + kTabH);
+          const v8h yrl = *reinterpret_cast<const v8h*>(ty + 2 * kTabH);
+          const v8h yil = *reinterpret_cast<const v8h*>(ty + 3 * kTabH);
+          const v8h xrh = *reinterpret_cast<const v8h*>(tx);
+          const v8h xih = *reinterpret_cast<const v8h*>(tx + kTabH);
+          const v8h xrl = *reinterpret_cast<const v8h*>(tx + 2 * kTabH);
+          const v8h xil = *reinterpret_cast<const v8h*>(tx + 3 * kTabH);
           const v8h nyih = -yih, nyil = -yil;
           // Re += yr xr - yi xi,  Im += yr xi + yi xr  (each as hi*hi + hi*lo + lo*hi)
           cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xrh, cr, 0, 0, 0);
@@ -391,29 +411,33 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
         }
       }
     }
-    // accumulator element r of this lane is (row (r&3) + 4 lk + 8 (r>>2), column li) of the quadrant
-    const float* f = ffs + 12 * z;
-    const int m = m0 + 32 * wx + li, ms = m < a.nx / 2 ? m : m - a.nx;
-    const float kx = (float)ms / (float)a.lx;
+    // accumulator element r of this lane is (row (r&3) + 4 lk + 8 (r>>2), column li) of the
+    // quadrant: V += f_z(|k|) S_z, the running sum kept in the output until the last species,
+    // which applies the prefactor and the band limit
+    if (tj < TWe) {
+      const float* f = ffs + 12 * z;
+      // the element coordinates are recomputed here on every species rather than held in
+      // registers across the contraction loop (the opaque copy stops their hoisting)
+      int tib = 32 * wy + 4 * lk;
+      asm volatile("" : "+v"(tib));
+      const int m = m0 + tj, ms = m < a.nx / 2 ? m : m - a.nx;
+      const float kx = (float)ms / (float)a.lx;
+      const int nm = a.nmax[m];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int n = n0 + 32 * wy + (r & 3) + 4 * lk + 8 * (r >> 2), ns = n < a.ny / 2 ? n : n - a.ny;
-      const float ky = (float)ns / (float)a.ly;
-      const float fz = form_factor(f, kx * kx + ky * ky);
-      vr[r] = fmaf(fz, cr[r], vr[r]);
-      vi[r] = fmaf(fz, ci[r], vi[r]);
-    }
-  }
-  const int tj = 32 * wx + li;
-  if (tj < TWe) {
-    const int m = m0 + tj;
-    const int nm = a.nmax[m];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int ti = 32 * wy + (r & 3) + 4 * lk + 8 * (r >> 2);
-      if (ti >= THe) continue;
-      const int n = n0 + ti, ns = n < a.ny / 2 ? n : n - a.ny, an = ns < 0 ? -ns : ns;
-      put(n, m, an <= nm ? make_float2(vr[r] * a.pref, vi[r] * a.pref) : make_float2(0.f, 0.f));
+      for (int r = 0; r < 16; ++r) {
+        const int ti = tib + (r & 3) + 8 * (r >> 2);
+        if (ti >= THe) continue;
+        const int n = n0 + ti, ns = n < a.ny / 2 ? n : n - a.ny, an = ns < 0 ? -ns : ns;
+        const float ky = (float)ns / (float)a.ly;
+        const float fz = form_factor(f, kx * kx + ky * ky);
+        float2 v = z == zfirst ? make_float2(0.f, 0.f) : out[(size_t)n * a.nx + m];
+        v.x = fmaf(fz, cr[r], v.x);
+        v.y = fmaf(fz, ci[r], v.y);
+        if (z == zlast)
+          put(n, m, an <= nm ? make_float2(v.x * a.pref, v.y * a.pref) : make_float2(0.f, 0.f));
+        else
+          out[(size_t)n * a.nx + m] = v;
+      }
     }
   }
 }
