@@ -162,6 +162,7 @@ __global__ __launch_bounds__(256) void k_atom_phase(const float* xyz, const int*
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __fp16 h2 __attribute__((ext_vector_type(2)));   // the packing builtin's type
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 // the fp16 pair (x0 - hi[0], x1 - hi[1]) rounded to nearest, hi being the packed fp16 high parts
 // of x0 and x1: one mixed-precision fused multiply-add per half (x - hi is exact in fp32)
 __device__ __forceinline__ h2 split_lo(float x0, float x1, h2 hi) {
@@ -394,7 +395,9 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
           const v8h xih = *reinterpret_cast<const v8h*>(tx + kTabH);
           const v8h xrl = *reinterpret_cast<const v8h*>(tx + 2 * kTabH);
           const v8h xil = *reinterpret_cast<const v8h*>(tx + 3 * kTabH);
-          const v8h nyih = -yih, nyil = -yil;
+          // -yi by flipping the two sign bits of each packed word (one XOR per 32 bits)
+          const v8h nyih = __builtin_bit_cast(v8h, __builtin_bit_cast(v4u, yih) ^ 0x80008000u);
+          const v8h nyil = __builtin_bit_cast(v8h, __builtin_bit_cast(v4u, yil) ^ 0x80008000u);
           // Re += yr xr - yi xi,  Im += yr xi + yi xr  (each as hi*hi + hi*lo + lo*hi)
           cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xrh, cr, 0, 0, 0);
           ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xih, ci, 0, 0, 0);
@@ -636,7 +639,8 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
         const v8h eih = *reinterpret_cast<const v8h*>(&Et[1][ar][kb]);
         const v8h erl = *reinterpret_cast<const v8h*>(&Et[2][ar][kb]);
         const v8h eil = *reinterpret_cast<const v8h*>(&Et[3][ar][kb]);
-        const v8h neih = -eih, neil = -eil;
+        const v8h neih = __builtin_bit_cast(v8h, __builtin_bit_cast(v4u, eih) ^ 0x80008000u);
+        const v8h neil = __builtin_bit_cast(v8h, __builtin_bit_cast(v4u, eil) ^ 0x80008000u);
         const v8h hrh = *reinterpret_cast<const v8h*>(&Ht[0][hc][kb]);
         const v8h hih = *reinterpret_cast<const v8h*>(&Ht[1][hc][kb]);
         const v8h hrl = *reinterpret_cast<const v8h*>(&Ht[2][hc][kb]);
