@@ -107,7 +107,7 @@ def test_binning_bit_exact(case):
 
 @pytest.mark.parametrize("split16", [1, 0])
 @pytest.mark.parametrize("case", ["c1", "nonsquare", "no-bandlimit", "half-plane-128",
-                                  "half-plane-256x128", "half-plane-off-128"])
+                                  "half-plane-256x128", "half-plane-off-128", "three-species"])
 def test_potentials_match_oracle(case, split16):
     if case == "c1":
         w = make_workload("c1", n_snap=3)
@@ -121,6 +121,17 @@ def test_potentials_match_oracle(case, split16):
         ff = form_factor_table(["A", "B"])
         if case.startswith("half-plane-off"):
             spec.bandlimit = 0.0
+    elif case == "three-species":
+        # the species sum of a slice runs through the output map: species 1 only in the top slice,
+        # so the other slices go from species 0 straight to species 2; no atoms at all in slice 2
+        spec, pos, species = _random_specimen(128, 128, 20.0, 20.0, [2.0, 2.0, 2.0, 2.0], 90, 2, 4)
+        rng = np.random.default_rng(44)
+        species = rng.integers(0, 3, size=pos.shape[1]).astype(np.int32)
+        zs = np.where(species == 1, rng.uniform(0.0, 2.0, size=pos.shape[:2]),
+                      np.where(rng.random(size=pos.shape[:2]) < 0.5, rng.uniform(2.0, 4.0, size=pos.shape[:2]),
+                               rng.uniform(6.0, 8.0, size=pos.shape[:2])))
+        pos[..., 2] = zs.astype(np.float32)
+        ff = form_factor_table(["A", "B", "BN-N"])
     else:
         spec, pos, species = _random_specimen(64, 32, 12.0, 7.5, [2.0, 3.0, 1.5], 70, 2, 2,
                                               outside=3)
