@@ -566,11 +566,13 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
       for (int m = m0 + tid; m < m0 + TWe; m += 256) any |= (a.nmax[m] >= minabs_n);
       if (!__syncthreads_or(any)) continue;     // also: the previous fill's readers are done
       used = 1;
-      // H and ky H for (kx = m0 + c, ky rows n0 + 8 kb + q): 8 consecutive ky per thread
+      // H and ky H for (kx = m0 + c, ky rows n0 + 8 kb + q): 8 consecutive ky per thread, each
+      // component split as hi = fp16 (round toward zero) and lo = fp16(x - hi) for the pairs of
+      // consecutive rows that share a packed word
       {
         const int c = tid & 63, kb = tid >> 6;
         const int m = m0 + c;
-        _Float16 hv[8][8];
+        float comps[4][8];   // Re H, Im H, Re ky H, Im ky H
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int n = n0 + 8 * kb + q;
@@ -583,26 +585,28 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
             const float2 g = G[(size_t)n * a.nx + m];
             h = make_float2(g.x * v, -g.y * v);
           }
-          const float2 hp = make_float2(ky * h.x, ky * h.y);
-          const float comps[4] = {h.x, h.y, hp.x, hp.y};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const _Float16 hi = (_Float16)comps[u];
-            hv[2 * u][q] = hi;                                   // high parts: 0 Re H, 2 Im H, ...
-            hv[2 * u + 1][q] = (_Float16)(comps[u] - (float)hi); // low parts
-          }
+          comps[0][q] = h.x;
+          comps[1][q] = h.y;
+          comps[2][q] = ky * h.x;
+          comps[3][q] = ky * h.y;
         }
         // table order: 0 Re H hi, 1 Im H hi, 2 Re H lo, 3 Im H lo, 4..7 the same for ky H
-        const int order[8] = {0, 2, 1, 3, 4, 6, 5, 7};
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          v8h pk;
+        for (int u = 0; u < 4; ++u) {
+          v4u hi, lo;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) pk[q] = hv[u][q];
-          *reinterpret_cast<v8h*>(&Ht[order[u]][c][8 * kb]) = pk;
+          for (int j = 0; j < 4; ++j) {
+            const h2 hh = __builtin_amdgcn_cvt_pkrtz(comps[u][2 * j], comps[u][2 * j + 1]);
+            hi[j] = __builtin_bit_cast(unsigned, hh);
+            lo[j] = __builtin_bit_cast(unsigned, split_lo(comps[u][2 * j], comps[u][2 * j + 1], hh));
+          }
+          const int th = (u >> 1) * 4 + (u & 1);
+          *reinterpret_cast<v4u*>(&Ht[th][c][8 * kb]) = hi;
+          *reinterpret_cast<v4u*>(&Ht[th + 2][c][8 * kb]) = lo;
         }
       }
-      // y phases of the 64 atoms at ky rows n0 + 8 kb .. + 7 (exact start, unit steps)
+      // y phases of the 64 atoms at ky rows n0 + 8 kb .. + 7 (exact start, unit steps), split as
+      // above
       {
         const int at = tid & 63, kb = tid >> 6;
         const int n = n0 + 8 * kb;
@@ -614,21 +618,27 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
           f = phase_factor(sidx, rec[at].uy);
           st = rec[at].sy;
         }
-        v8h rh, ih, rl, il;
+        float2 fq[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           if (q == qw && live) f = phase_factor(n + q - a.ny, rec[at].uy);
-          const _Float16 a_hi = (_Float16)f.x, b_hi = (_Float16)f.y;
-          rh[q] = a_hi;
-          ih[q] = b_hi;
-          rl[q] = (_Float16)(f.x - (float)a_hi);
-          il[q] = (_Float16)(f.y - (float)b_hi);
+          fq[q] = f;
           f = cmul(f, st);
         }
-        *reinterpret_cast<v8h*>(&Et[0][at][8 * kb]) = rh;
-        *reinterpret_cast<v8h*>(&Et[1][at][8 * kb]) = ih;
-        *reinterpret_cast<v8h*>(&Et[2][at][8 * kb]) = rl;
-        *reinterpret_cast<v8h*>(&Et[3][at][8 * kb]) = il;
+        v4u rh, ih, rl, il;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const h2 a_hi = __builtin_amdgcn_cvt_pkrtz(fq[2 * j].x, fq[2 * j + 1].x);
+          const h2 b_hi = __builtin_amdgcn_cvt_pkrtz(fq[2 * j].y, fq[2 * j + 1].y);
+          rh[j] = __builtin_bit_cast(unsigned, a_hi);
+          ih[j] = __builtin_bit_cast(unsigned, b_hi);
+          rl[j] = __builtin_bit_cast(unsigned, split_lo(fq[2 * j].x, fq[2 * j + 1].x, a_hi));
+          il[j] = __builtin_bit_cast(unsigned, split_lo(fq[2 * j].y, fq[2 * j + 1].y, b_hi));
+        }
+        *reinterpret_cast<v4u*>(&Et[0][at][8 * kb]) = rh;
+        *reinterpret_cast<v4u*>(&Et[1][at][8 * kb]) = ih;
+        *reinterpret_cast<v4u*>(&Et[2][at][8 * kb]) = rl;
+        *reinterpret_cast<v4u*>(&Et[3][at][8 * kb]) = il;
       }
       __syncthreads();
       const int ar = 32 * wa + li, hc = 32 * wk + li;
