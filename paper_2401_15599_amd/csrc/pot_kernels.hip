@@ -12,9 +12,12 @@
 namespace tacaw {
 
 // ---------------------------------------------------------------------------------------------
-// binning: one workgroup per snapshot, stable counting sort by key = slice * n_species + species
-constexpr int kBinThreads = 256;
-
+// binning: one workgroup per snapshot, stable counting sort by key = slice * n_species + species.
+// The NW wavefronts of a workgroup own contiguous atom ranges (wave w: [w R, (w + 1) R)) and a
+// counter row each: counts per (wave, key), then a scan in (key, wave) order gives every wave its
+// start position per key, then each wave scatters its range in order, 64 atoms at a time, ranking
+// a lane among the lanes of equal key by matching the key bits with ballots.  The result is the
+// stable order (ascending atom index within each key).
 __device__ __forceinline__ int slice_of(float zf, const double* b, int S) {
   const double z = (double)zf;
   if (!(z >= b[0]) || !(z < b[S])) return -1;
@@ -26,70 +29,77 @@ __device__ __forceinline__ int slice_of(float zf, const double* b, int S) {
   return lo;
 }
 
-__global__ __launch_bounds__(kBinThreads) void k_bin(const float* xyz, const int* species,
-                                                     int n_atoms, int nsp, const double* bounds,
-                                                     int S, int* offsets, int* order, int* n_out) {
+__global__ __launch_bounds__(1024) void k_bin(const float* xyz, const int* species, int n_atoms,
+                                              int nsp, const double* bounds, int S, int* offsets,
+                                              int* order, int* n_out) {
   extern __shared__ int sh[];
-  const int K = S * nsp;
-  int* cnt = sh;                       // [K] counts, then running cursors
-  int* keys = sh + K;                  // [256] keys of the current chunk
-  int* part = keys + kBinThreads;      // [256] scan partials / outside counts
-  const int t = blockIdx.x, tid = threadIdx.x;
+  const int K = S * nsp, NW = (int)blockDim.x >> 6;
+  const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int* cur = sh;                       // [NW][K] counts, then start positions
+  int* part = sh + NW * K;             // [blockDim] scan partials and outside counts
   const float* X = xyz + (size_t)t * n_atoms * 3;
-  for (int i = tid; i < K; i += kBinThreads) cnt[i] = 0;
+  const int R = (n_atoms + NW - 1) / NW;
+  const int j0 = min(n_atoms, w * R), j1 = min(n_atoms, j0 + R);
+  auto key_of = [&](int j) {
+    const int sl = slice_of(X[3 * j + 2], bounds, S);
+    return sl < 0 ? -1 : sl * nsp + species[j];
+  };
+  for (int i = tid; i < NW * K; i += blockDim.x) cur[i] = 0;
   __syncthreads();
   int outside = 0;
-  for (int j = tid; j < n_atoms; j += kBinThreads) {
-    int s = slice_of(X[3 * j + 2], bounds, S);
-    if (s < 0) { ++outside; continue; }
-    atomicAdd(&cnt[s * nsp + species[j]], 1);
+  for (int j = j0 + lane; j < j1; j += 64) {
+    const int key = key_of(j);
+    if (key < 0) ++outside;
+    else atomicAdd(&cur[w * K + key], 1);
   }
   part[tid] = outside;
   __syncthreads();
   if (tid == 0) {
     int tot = 0;
-    for (int i = 0; i < kBinThreads; ++i) tot += part[i];
+    for (int i = 0; i < (int)blockDim.x; ++i) tot += part[i];
     if (n_out) n_out[t] = tot;
   }
   __syncthreads();
-  // exclusive scan of cnt: each thread owns a contiguous range
-  const int per = (K + kBinThreads - 1) / kBinThreads;
-  const int a0 = tid * per, a1 = min(K, a0 + per);
+  // exclusive scan over (key, wave): each thread owns a contiguous key range
+  const int per = (K + blockDim.x - 1) / blockDim.x;
+  const int a0 = min(K, tid * per), a1 = min(K, a0 + per);
   int local = 0;
-  for (int i = a0; i < a1; ++i) local += cnt[i];
+  for (int k = a0; k < a1; ++k)
+    for (int v = 0; v < NW; ++v) local += cur[v * K + k];
   part[tid] = local;
   __syncthreads();
   if (tid == 0) {
     int run = 0;
-    for (int i = 0; i < kBinThreads; ++i) { int v = part[i]; part[i] = run; run += v; }
+    for (int i = 0; i < (int)blockDim.x; ++i) { const int v = part[i]; part[i] = run; run += v; }
   }
   __syncthreads();
   int run = part[tid];
   int* off = offsets + (size_t)t * (K + 1);
-  for (int i = a0; i < a1; ++i) { int v = cnt[i]; cnt[i] = run; off[i] = run; run += v; }
-  if (tid == kBinThreads - 1) off[K] = part[tid] + local;
+  for (int k = a0; k < a1; ++k) {
+    off[k] = run;
+    for (int v = 0; v < NW; ++v) { const int c = cur[v * K + k]; cur[v * K + k] = run; run += c; }
+  }
+  if (tid == (int)blockDim.x - 1) off[K] = part[tid] + local;
   __syncthreads();
-  // stable scatter in chunks of 256 atoms
+  // ordered scatter of each wave's range
+  const int nbits = K > 1 ? 32 - __builtin_clz((unsigned)(K - 1)) : 0;
+  const unsigned long long below = (1ull << lane) - 1ull;
   int* ord = order + (size_t)t * n_atoms;
-  for (int base = 0; base < n_atoms; base += kBinThreads) {
-    const int j = base + tid;
-    int key = -1;
-    if (j < n_atoms) {
-      int s = slice_of(X[3 * j + 2], bounds, S);
-      if (s >= 0) key = s * nsp + species[j];
+  int* mycur = cur + w * K;
+  for (int base = j0; base < j1; base += 64) {
+    const int j = base + lane;
+    const int key = j < j1 ? key_of(j) : -1;
+    unsigned long long match = __ballot(key >= 0);
+    for (int b = 0; b < nbits; ++b) {
+      const unsigned long long bal = __ballot(key >= 0 && ((key >> b) & 1));
+      match &= ((key >> b) & 1) ? bal : ~bal;
     }
-    keys[tid] = key;
-    __syncthreads();
-    int rank = 0, last = 1;
     if (key >= 0) {
-      for (int i = 0; i < tid; ++i) rank += (keys[i] == key);
-      for (int i = tid + 1; i < kBinThreads; ++i)
-        if (keys[i] == key) { last = 0; break; }
-      ord[cnt[key] + rank] = j;
+      const int rank = __popcll(match & below);
+      ord[mycur[key] + rank] = j;
+      // the highest lane of the group advances the cursor after every lane has read it
+      if ((match >> lane) == 1ull) mycur[key] += rank + 1;
     }
-    __syncthreads();
-    if (key >= 0 && last) cnt[key] += rank + 1;
-    __syncthreads();
   }
 }
 
@@ -97,9 +107,13 @@ hipError_t launch_bin_atoms(const float* xyz, const int* species, int n_snap, in
                             int n_species, const double* bounds, int S, int* offsets, int* order,
                             int* n_out, hipStream_t st) {
   const int K = S * n_species;
-  const int lds = (K + 2 * kBinThreads) * (int)sizeof(int);
+  // as many wavefronts as keep their counter rows within 64 KB of LDS (K <= 16384 allows one)
+  int nw = 16;
+  while (nw > 1 && (long)nw * K * (int)sizeof(int) > 65536) nw /= 4;
+  const int threads = 64 * nw;
+  const int lds = (nw * K + threads) * (int)sizeof(int);
   hipFuncSetAttribute((const void*)k_bin, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipLaunchKernelGGL(k_bin, dim3(n_snap), dim3(kBinThreads), lds, st, xyz, species, n_atoms,
+  hipLaunchKernelGGL(k_bin, dim3(n_snap), dim3(threads), lds, st, xyz, species, n_atoms,
                      n_species, bounds, S, offsets, order, n_out);
   return hipGetLastError();
 }
