@@ -105,7 +105,8 @@ int tacaw_energy_axis(int32_t n_e, double dt_fs, double* e_ev /* host [n_e] */);
  * z_0 = z0 and z_{s+1} = z_s + dz[s] accumulated in slice order.  Atoms outside [z_0, z_S) belong to
  * no slice and are dropped (counted in *n_outside).
  *   xyz       dev [n_snap][n_atoms][3] float positions
- *   species   dev [n_atoms] int32 in [0, n_species)
+ *   species   dev [n_atoms] int32 in [0, n_species) (an atom with any other value is not binned
+ *             and counts as outside the slab)
  *   offsets   dev out [n_snap][S*n_species + 1] int32: atoms of (t, s, Z) are
  *             order[t][offsets[t][s*n_species+Z] .. offsets[t][s*n_species+Z+1])
  *   order     dev out [n_snap][n_atoms] int32 atom indices, sorted by (slice, species, index)

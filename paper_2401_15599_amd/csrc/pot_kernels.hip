@@ -40,9 +40,12 @@ __global__ __launch_bounds__(1024) void k_bin(const float* xyz, const int* speci
   const float* X = xyz + (size_t)t * n_atoms * 3;
   const int R = (n_atoms + NW - 1) / NW;
   const int j0 = min(n_atoms, w * R), j1 = min(n_atoms, j0 + R);
+  // key of atom j, or -1 outside the slab (or, for memory safety, with a species outside
+  // [0, nsp))
   auto key_of = [&](int j) {
     const int sl = slice_of(X[3 * j + 2], bounds, S);
-    return sl < 0 ? -1 : sl * nsp + species[j];
+    const int z = species[j];
+    return (sl < 0 || (unsigned)z >= (unsigned)nsp) ? -1 : sl * nsp + z;
   };
   for (int i = tid; i < NW * K; i += blockDim.x) cur[i] = 0;
   __syncthreads();

@@ -78,11 +78,28 @@ def _oracle_csr(pos, species, spec, nsp):
     return offs, orders, nout
 
 
-@pytest.mark.parametrize("case", ["c1", "ragged"])
+@pytest.mark.parametrize("case", ["c1", "ragged", "keys-1400", "keys-4200", "five-atoms",
+                                  "bad-species"])
 def test_binning_bit_exact(case):
     if case == "c1":
         w = make_workload("c1", n_snap=3)
         spec, pos, species, nsp = w, w.positions, w.species, 1
+    elif case.startswith("keys"):
+        # 1400 keys: four wavefronts' counter rows fit the kernel's LDS budget; 4200: one
+        S = 700 if case == "keys-1400" else 2100
+        spec, pos, species = _random_specimen(32, 32, 8.0, 8.0, [0.25] * S, 5000, 2, 9, outside=7)
+        nsp = 2
+    elif case == "bad-species":
+        # species values outside [0, n_species) are not binned: the expected CSR is that of the
+        # same atoms moved outside the slab
+        spec, pos, species = _random_specimen(32, 16, 8.0, 4.0, [1.0, 2.5, 0.7, 3.0], 37, 2, 13)
+        nsp = 2
+        species[[3, 20]] = [2, -1]
+    elif case == "five-atoms":
+        # fewer atoms than wavefronts: most wavefronts own empty ranges
+        spec, pos, species = _random_specimen(32, 16, 8.0, 4.0, [1.0, 2.5, 0.7, 3.0], 5, 3, 11,
+                                              outside=1)
+        nsp = 2
     else:
         spec, pos, species = _random_specimen(32, 16, 8.0, 4.0, [1.0, 2.5, 0.7, 3.0], 37, 5, 1,
                                               outside=4)
@@ -94,7 +111,9 @@ def test_binning_bit_exact(case):
     nout = torch.empty((T,), dtype=torch.int32, device=DEV)
     tw.tacaw_bin_atoms(ctx(), tw.specimen_from(spec), _gpu(pos), _gpu(species), nsp, offs, order,
                        nout)
-    ro, rord, rn = _oracle_csr(pos, species, spec, nsp)
+    ref_pos = pos.copy()
+    ref_pos[:, (species < 0) | (species >= nsp), 2] = -1.0
+    ro, rord, rn = _oracle_csr(ref_pos, species, spec, nsp)
     offs, order, nout = offs.cpu().numpy(), order.cpu().numpy(), nout.cpu().numpy()
     for t in range(T):
         np.testing.assert_array_equal(offs[t], ro[t])
