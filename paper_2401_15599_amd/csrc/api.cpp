@@ -817,7 +817,17 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
                                n_outside, st),
               "bin kernel");
     float* ffd = upload_vec(ctx, ff_f32(ff, n_species), st, "ff");
-    int* nmax = upload_vec(ctx, bandlimit_table(*spec), st, "bl");
+    const std::vector<int> bl = bandlimit_table(*spec);
+    int* nmax = upload_vec(ctx, bl, st, "bl");
+    // the inverse FFT skips the columns and rows the band limit leaves zero
+    int kxb = band_columns(bl), kyb = *std::max_element(bl.begin(), bl.end());
+    if (kxb >= spec->nx / 2) kxb = -1;
+    if (kyb >= spec->ny / 2) kyb = -1;
+    // bytes per pixel of the inverse FFT: column pass reads the kept rows of the kept columns and
+    // writes the kept columns, row pass reads the kept columns and writes every real pixel
+    const double fc = kxb < 0 ? 1.0 : (2.0 * kxb + 1.0) / spec->nx;
+    const double fr = kyb < 0 ? 1.0 : (2.0 * kyb + 1.0) / spec->ny;
+    const double ifft_bytes = 8.0 * fc * fr + 16.0 * fc + 4.0;
     const size_t img = (size_t)spec->nx * spec->ny;
     const size_t budget = (size_t)1 << 30;   // bytes of complex k-space maps per pass
     int snaps_per = (int)std::max<size_t>(1, budget / (img * 8 * S));
@@ -850,8 +860,9 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
       timed_launch(ctx, st, "sf", 8.0 * img * nt * S, [&] {
         hip_check(launch_structure_factor(a, st), "structure-factor kernel");
       });
-      timed_launch(ctx, st, "pot_ifft", 36.0 * img * nt * S, [&] {
-        hip_check(launch_ifft2_real(spec->nx, spec->ny, vk, V + (size_t)t0 * S * img, nt * S, st),
+      timed_launch(ctx, st, "pot_ifft", ifft_bytes * img * nt * S, [&] {
+        hip_check(launch_ifft2_real(spec->nx, spec->ny, vk, V + (size_t)t0 * S * img, nt * S, kxb,
+                                    kyb, st),
                   "potential inverse FFT");
       });
     }

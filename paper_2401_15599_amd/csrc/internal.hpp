@@ -85,6 +85,9 @@ struct PlainArgs {
   const void* in;
   void* out;
   int n_img, nx, ny, C;
+  // inverse transform of band-limited maps: columns kxb < m < nx - kxb and rows kyb < n < ny - kyb
+  // are zero on input and are neither read nor transformed (-1: no band)
+  int kxb = -1, kyb = -1;
 };
 
 // -------- launchers (defined in the .hip files) --------
@@ -129,7 +132,8 @@ struct SfArgs {
   int split16;             // fp16 hi/lo split operands on the f16 matrix cores (else fp32 MFMA)
 };
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st);
-hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hipStream_t st);
+hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, int kxb, int kyb,
+                             hipStream_t st);
 hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, hipStream_t st);
 struct PgArgs {
   const float* xyz; const int* order; const int* offsets; const float* ff;

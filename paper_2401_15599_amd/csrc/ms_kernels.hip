@@ -606,7 +606,10 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_row_plain(PlainArg
     } else {
       const float2* in = (const float2*)a.in + off;
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = in[l + L * j];
+      for (int j = 0; j < E; ++j) {
+        const int m = l + L * j;
+        v[j] = (a.kxb >= 0 && m > a.kxb && m < N - a.kxb) ? make_float2(0.f, 0.f) : in[m];
+      }
     }
     FFT<P>::template run<INV>(v, tw, lds, l, tab);
     if constexpr (REAL_OUT) {
@@ -636,12 +639,15 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col_plain(PlainArg
   for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
     const size_t ioff = (size_t)(task / tpi) * nx * N;
     const int col0 = (int)(task % tpi) * C;
+    // a tile of columns that are all zero stays zero (and the row pass does not read it)
+    if (a.kxb >= 0 && col0 > a.kxb && col0 + C - 1 < nx - a.kxb) continue;
     const float2* in = (const float2*)a.in + ioff;
     float2* out = (float2*)a.out + ioff;
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      tile[c * CS + P::pad(r)] = in[(size_t)r * nx + col0 + c];
+      const bool zero = a.kyb >= 0 && r > a.kyb && r < N - a.kyb;
+      tile[c * CS + P::pad(r)] = zero ? make_float2(0.f, 0.f) : in[(size_t)r * nx + col0 + c];
     }
     __syncthreads();
     for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
@@ -912,10 +918,11 @@ static int plain_cols(int nx, int n) {
   return c;
 }
 
-hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hipStream_t st) {
+hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, int kxb, int kyb,
+                             hipStream_t st) {
   if (n_img <= 0) return hipSuccess;
   hipError_t e = hipErrorInvalidValue;
-  PlainArgs a{vk, vk, n_img, nx, ny, plain_cols(nx, ny)};
+  PlainArgs a{vk, vk, n_img, nx, ny, plain_cols(nx, ny), kxb, kyb};
   with_plan(ny, 0, [&](auto p) {
     using P = decltype(p);
     const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
@@ -925,7 +932,7 @@ hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, hi
     e = hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  PlainArgs b{vk, V, n_img, nx, ny, 0};
+  PlainArgs b{vk, V, n_img, nx, ny, 0, kxb, -1};
   with_plan(nx, 0, [&](auto p) {
     using P = decltype(p);
     long tasks = (long)n_img * ny;
