@@ -824,10 +824,12 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
     if (kxb >= spec->nx / 2) kxb = -1;
     if (kyb >= spec->ny / 2) kyb = -1;
     // bytes per pixel of the inverse FFT: column pass reads the kept rows of the kept columns and
-    // writes the kept columns, row pass reads the kept columns and writes every real pixel
+    // writes the kept columns, row pass reads those and writes every real pixel; with two maps per
+    // transform (A + iB) the column writes and row reads are shared by the pair
     const double fc = kxb < 0 ? 1.0 : (2.0 * kxb + 1.0) / spec->nx;
     const double fr = kyb < 0 ? 1.0 : (2.0 * kyb + 1.0) / spec->ny;
-    const double ifft_bytes = 8.0 * fc * fr + 16.0 * fc + 4.0;
+    const bool paired = spec->bandlimit > 0.0 && spec->bandlimit < 1.0;
+    const double ifft_bytes = 8.0 * fc * fr + (paired ? 8.0 : 16.0) * fc + 4.0;
     const size_t img = (size_t)spec->nx * spec->ny;
     const size_t budget = (size_t)1 << 30;   // bytes of complex k-space maps per pass
     int snaps_per = (int)std::max<size_t>(1, budget / (img * 8 * S));
@@ -861,8 +863,10 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
         hip_check(launch_structure_factor(a, st), "structure-factor kernel");
       });
       timed_launch(ctx, st, "pot_ifft", ifft_bytes * img * nt * S, [&] {
+        // two maps per complex transform when the band limit removes every Nyquist term
+        const int pair = (spec->bandlimit > 0.0 && spec->bandlimit < 1.0) ? 1 : 0;
         hip_check(launch_ifft2_real(spec->nx, spec->ny, vk, V + (size_t)t0 * S * img, nt * S, kxb,
-                                    kyb, st),
+                                    kyb, pair, offs, t0, S, n_species, st),
                   "potential inverse FFT");
       });
     }

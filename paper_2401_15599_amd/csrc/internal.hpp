@@ -88,6 +88,14 @@ struct PlainArgs {
   // inverse transform of band-limited maps: columns kxb < m < nx - kxb and rows kyb < n < ny - kyb
   // are zero on input and are neither read nor transformed (-1: no band)
   int kxb = -1, kyb = -1;
+  // inverse transform to real maps, two at a time: maps 2p and 2p + 1 (Hermitian spectra A, B)
+  // are transformed as A + iB, whose real and imaginary parts are the two real maps (only for
+  // spectra without Nyquist terms, whose missing partners would leak into the other map)
+  int pair = 0;
+  // slice maps without atoms (CSR offsets [t][S * nsp + 1]; map m is slice m % S of snapshot
+  // t0 + m / S) are written as exact zeros instead of their partner's rounding residue
+  const int* csr = nullptr;
+  int csr_t0 = 0, csr_S = 1, csr_nsp = 1;
 };
 
 // -------- launchers (defined in the .hip files) --------
@@ -133,7 +141,7 @@ struct SfArgs {
 };
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st);
 hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, int kxb, int kyb,
-                             hipStream_t st);
+                             int pair, const int* csr, int t0, int S, int nsp, hipStream_t st);
 hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, hipStream_t st);
 struct PgArgs {
   const float* xyz; const int* order; const int* offsets; const float* ff;

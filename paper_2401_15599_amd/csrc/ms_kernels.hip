@@ -592,12 +592,17 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_row_plain(PlainArg
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
   const float2* tab = fft_table_init<P>();
-  const long n_tasks = (long)a.n_img * a.ny;
+  // paired (real output only): task = (pair p, row y) reads row y of image 2p and writes the real
+  // part to image 2p and the imaginary part to image 2p + 1 (if there is one)
+  const bool pair = REAL_OUT && a.pair;
+  const long n_rows = pair ? (long)((a.n_img + 1) / 2) * a.ny : (long)a.n_img * a.ny;
+  const long n_tasks = n_rows;
   const long stride = (long)gridDim.x * kWaves * LINES;
   for (long base = ((long)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
     const long task = base + line;
     if ((!P::FULL && line >= LINES) || task >= n_tasks) continue;
-    const size_t off = (size_t)task * N;
+    const long img = pair ? 2 * (task / a.ny) : task / a.ny;
+    const size_t off = ((size_t)img * a.ny + (size_t)(task % a.ny)) * N;
     float2 v[E];
     if constexpr (REAL_IN) {
       const float* in = (const float*)a.in + off;
@@ -613,9 +618,22 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_row_plain(PlainArg
     }
     FFT<P>::template run<INV>(v, tw, lds, l, tab);
     if constexpr (REAL_OUT) {
+      auto empty = [&](long m) {
+        if (!a.csr) return false;
+        const int* o = a.csr + (size_t)(a.csr_t0 + m / a.csr_S) * (a.csr_S * a.csr_nsp + 1) +
+                       (m % a.csr_S) * a.csr_nsp;
+        return o[0] == o[a.csr_nsp];
+      };
       float* out = (float*)a.out + off;
+      const bool za = pair && empty(img);
 #pragma unroll
-      for (int j = 0; j < E; ++j) out[l + L * j] = v[j].x;
+      for (int j = 0; j < E; ++j) out[l + L * j] = za ? 0.f : v[j].x;
+      if (pair && img + 1 < a.n_img) {
+        float* out2 = out + (size_t)a.ny * N;
+        const bool zb = empty(img + 1);
+#pragma unroll
+        for (int j = 0; j < E; ++j) out2[l + L * j] = zb ? 0.f : v[j].y;
+      }
     } else {
       float2* out = (float2*)a.out + off;
 #pragma unroll
@@ -635,19 +653,31 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col_plain(PlainArg
   const float2* tab = fft_table_init<P>();
   const int C = a.C, nx = a.nx;
   const int tpi = nx / C;
-  const long n_tasks = (long)a.n_img * tpi;
+  // paired: task = (pair p, column tile) transforms A + iB of images 2p, 2p + 1 into image 2p
+  const int n_im = a.pair ? (a.n_img + 1) / 2 : a.n_img;
+  const long n_tasks = (long)n_im * tpi;
   for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
-    const size_t ioff = (size_t)(task / tpi) * nx * N;
+    const long img = a.pair ? 2 * (task / tpi) : task / tpi;
+    const size_t ioff = (size_t)img * nx * N;
     const int col0 = (int)(task % tpi) * C;
     // a tile of columns that are all zero stays zero (and the row pass does not read it)
     if (a.kxb >= 0 && col0 > a.kxb && col0 + C - 1 < nx - a.kxb) continue;
     const float2* in = (const float2*)a.in + ioff;
     float2* out = (float2*)a.out + ioff;
+    const bool second = a.pair && img + 1 < a.n_img;
     __syncthreads();
     for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
       int c = idx % C, r = idx / C;
       const bool zero = a.kyb >= 0 && r > a.kyb && r < N - a.kyb;
-      tile[c * CS + P::pad(r)] = zero ? make_float2(0.f, 0.f) : in[(size_t)r * nx + col0 + c];
+      float2 v = make_float2(0.f, 0.f);
+      if (!zero) {
+        v = in[(size_t)r * nx + col0 + c];
+        if (second) {
+          const float2 b = in[(size_t)nx * N + (size_t)r * nx + col0 + c];
+          v = make_float2(v.x - b.y, v.y + b.x);
+        }
+      }
+      tile[c * CS + P::pad(r)] = v;
     }
     __syncthreads();
     for (int cb = wave * LINES; cb < C; cb += kWaves * LINES) {
@@ -919,23 +949,24 @@ static int plain_cols(int nx, int n) {
 }
 
 hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, int kxb, int kyb,
-                             hipStream_t st) {
+                             int pair, const int* csr, int t0, int S, int nsp, hipStream_t st) {
   if (n_img <= 0) return hipSuccess;
   hipError_t e = hipErrorInvalidValue;
-  PlainArgs a{vk, vk, n_img, nx, ny, plain_cols(nx, ny), kxb, kyb};
+  PlainArgs a{vk, vk, n_img, nx, ny, plain_cols(nx, ny), kxb, kyb, pair};
+  const long n_im = pair ? (n_img + 1) / 2 : n_img;
   with_plan(ny, 0, [&](auto p) {
     using P = decltype(p);
     const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
-    long tasks = (long)n_img * (nx / a.C);
+    long tasks = n_im * (nx / a.C);
     int grid = (int)(tasks < 4096 ? tasks : 4096);
     hipLaunchKernelGGL((k_col_plain<P, true>), dim3(grid), dim3(kThreads), lds, st, a);
     e = hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  PlainArgs b{vk, V, n_img, nx, ny, 0, kxb, -1};
+  PlainArgs b{vk, V, n_img, nx, ny, 0, kxb, -1, pair, csr, t0, S, nsp};
   with_plan(nx, 0, [&](auto p) {
     using P = decltype(p);
-    long tasks = (long)n_img * ny;
+    long tasks = n_im * ny;
     long g = (tasks + kWaves * P::LINES - 1) / (kWaves * P::LINES);
     int grid = (int)(g < 4096 ? g : 4096);
     hipLaunchKernelGGL((k_row_plain<P, true, false, true>), dim3(grid), dim3(kThreads), 0, st, b);

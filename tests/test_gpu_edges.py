@@ -77,6 +77,17 @@ def test_slices_without_atoms():
     assert rel_l2(ex, ref) <= 1e-4
 
 
+def test_empty_slice_paired_with_an_occupied_one():
+    # band-limited maps are inverse-transformed two at a time (A + iB); an empty map stays exactly
+    # zero whichever side of its pair it is on, and an odd map count leaves the last one unpaired
+    spec, pos, species = _specimen(128, 24.0, [2.0] * 3, 40, 1, 5)
+    pos[..., 2] = np.float32(2.0) + pos[..., 2] % np.float32(2.0) * np.float32(0.5)   # slice 1 only
+    V, Vr, _ = _pipeline(spec, pos, species, PLANE)
+    assert np.all(V[:, 0] == 0.0) and np.all(V[:, 2] == 0.0)
+    assert np.any(V[:, 1] != 0.0)
+    assert rel_l2(V, Vr) <= 1e-5
+
+
 def test_smallest_grid_with_probe():
     spec, pos, species = _specimen(16, 4.0, [1.5, 1.5], 6, 3, 3)
     beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.05, defocus_a=10.0, cs_a=0.0,
