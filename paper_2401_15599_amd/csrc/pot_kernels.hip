@@ -273,6 +273,17 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
     return;
   }
   const int tj = 32 * wx + li;
+  // does any k of this wavefront's 32 x 32 quadrant pass the band limit?  A quadrant that does not
+  // skips its matrix-core products (its outputs are all zero); the tables are still generated
+  bool quad_live;
+  {
+    int minabs_q = 1 << 30;
+    for (int n = n0 + 32 * wy; n < min(n0 + THe, n0 + 32 * wy + 32); ++n) {
+      const int ns = n < a.ny / 2 ? n : n - a.ny;
+      minabs_q = min(minabs_q, ns < 0 ? -ns : ns);
+    }
+    quad_live = __ballot(tj < TWe && a.nmax[m0 + min(tj, TWe - 1)] >= minabs_q) != 0ull;
+  }
   for (int z = 0; z < a.n_species; ++z) {
     const int j0 = off[s * a.n_species + z], j1 = off[s * a.n_species + z + 1];
     if (j1 <= j0) continue;
@@ -389,7 +400,9 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
         }
       }
       __syncthreads();
-      if constexpr (!SPLIT) {
+      if (!quad_live) {
+        // no kept k in this quadrant
+      } else if constexpr (!SPLIT) {
         const int npair = (na + 1) >> 1;
         for (int p = 0; p < npair; ++p) {
           const float2 yv = ey[2 * p + lk][32 * wy + li];
