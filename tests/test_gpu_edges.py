@@ -88,6 +88,29 @@ def test_empty_slice_paired_with_an_occupied_one():
     assert rel_l2(V, Vr) <= 1e-5
 
 
+def test_empty_slices_across_snapshot_passes():
+    # 1024^2 with 65 slices: the potential build takes one snapshot per pass (its 1 GiB k-space
+    # budget), so the second pass starts at snapshot 1 and each pass pairs an odd number of maps;
+    # atoms only in the first 10 slices, the other 55 maps exactly zero
+    rng = np.random.default_rng(21)
+    S, A = 65, 24
+    pos = np.stack([rng.uniform(0, 60.0, (2, A)), rng.uniform(0, 60.0, (2, A)),
+                    rng.uniform(0, 4.9, (2, A))], axis=-1).astype(np.float32)
+    species = rng.integers(0, 2, A).astype(np.int32)
+    spec = SimpleNamespace(nx=1024, ny=1024, lx=60.0, ly=60.0, dz=np.full(S, 0.5), z0=0.0,
+                           bandlimit=2.0 / 3.0)
+    ff = form_factor_table(["A", "B"])
+    V = torch.empty((2, S, 1024, 1024), dtype=torch.float32, device=DEV)
+    tw.tacaw_build_potentials(tw.context(0), tw.specimen_from(spec), _gpu(pos), _gpu(species), ff, V)
+    torch.cuda.synchronize()
+    assert bool((V[:, 10:] == 0).all())
+    sel = [0, 3, 9]
+    Vr, _ = o_pot.potentials(pos, species, ff, SimpleNamespace(**{**vars(spec), "dz": np.full(10, 0.5)}))
+    for t in range(2):
+        for s in sel:
+            assert rel_l2(V[t, s].cpu().numpy(), Vr[t, s]) <= 1e-5, (t, s)
+
+
 def test_smallest_grid_with_probe():
     spec, pos, species = _specimen(16, 4.0, [1.5, 1.5], 6, 3, 3)
     beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.05, defocus_a=10.0, cs_a=0.0,
