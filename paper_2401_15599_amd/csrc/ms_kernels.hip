@@ -939,10 +939,11 @@ hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-// columns per tile of the plain column transform: a power of two that divides nx
+// columns per tile of the plain column transform: a power of two that divides nx.  Narrow tiles
+// keep the LDS tile small enough for several workgroups per CU (measured: 16 columns at 256
+// points and 8 from 512 on beat 32 and 16)
 static int plain_cols(int nx, int n) {
-  int c = (n <= 64) ? 64 : (n <= 256 ? 32 : 16);
-  if (n >= 1000) c = 8;
+  int c = (n <= 64) ? 64 : (n <= 128 ? 32 : (n <= 256 ? 16 : 8));
   if (c > nx) c = nx;
   while (c > 1 && nx % c != 0) c /= 2;
   return c;
