@@ -17,7 +17,11 @@ sum_q |phi(q)|^2 = sum_r |psi_S(r)|^2.
 Initial waves: a plane wave psi_0 = 1/sqrt(Nx Ny), or a STEM probe
   psi_0(k) proportional to A(k) exp(-i chi(k)) exp(-2 pi i k . r_p),
   A(k) = 1 when (lambda^2) (kx^2 + ky^2) <= alpha^2 (float64), chi = pi lambda df k^2 + pi Cs lambda^3 k^4 / 2,
-normalised to sum_r |psi_0(r)|^2 = 1.
+normalised to sum_r |psi_0(r)|^2 = 1.  Sign reading of the defocus: a probe at defocus df is the
+in-focus probe propagated forward by df in vacuum with the propagator above (its crossover lies df
+before the entrance plane); chi in terms of the angle theta = lambda |k| is the textbook
+(2 pi / lambda) (Cs theta^4 / 4 + df theta^2 / 2).  (The paper's Fe run defines its probe only by the
+convergence semi-angle.)
 """
 import math
 

@@ -118,3 +118,73 @@ def test_probe_is_normalised_and_centred_on_its_position():
     kx = np.fft.fftfreq(128, d=0.25)
     k = np.hypot(kx[None, :], kx[:, None])
     assert np.max(np.abs(a[k * wavelength(100e3) > 0.0301])) < 1e-10
+
+
+def test_probe_defocus_equals_free_space_propagation_of_the_focused_probe():
+    # chi's defocus term pi lambda df k^2 is exactly the phase of the (already pinned) Fresnel
+    # propagator over a thickness df: the probe at defocus df is the in-focus probe propagated
+    # forward by df in vacuum.  A wrong sign or factor of the defocus term fails by O(1).
+    spec = _spec(128, 128, 32.0, 32.0, [1.0], bandlimit=0.0)
+    pos = np.array([[13.0, 17.5]])
+    for e, alpha, df in ((100e3, 0.03, 50.0), (200e3, 0.02, -120.0)):
+        focused = SimpleNamespace(probe=True, energy_ev=e, alpha_rad=alpha, defocus_a=0.0,
+                                  cs_a=0.0, probe_xy=pos)
+        defocused = SimpleNamespace(probe=True, energy_ev=e, alpha_rad=alpha, defocus_a=df,
+                                    cs_a=0.0, probe_xy=pos)
+        psi_f = ms.initial_waves(spec, focused)[0]
+        psi_d = ms.initial_waves(spec, defocused)[0]
+        n = spec.nx * spec.ny
+        spec.dz = np.array([df])
+        phi = ms.propagate(psi_f, np.zeros((1, 128, 128)), spec, e)
+        np.testing.assert_allclose(phi, dft2(psi_d) / math.sqrt(n), atol=1e-12)
+        spec.dz = np.array([-df])
+        wrong = ms.propagate(psi_f, np.zeros((1, 128, 128)), spec, e)
+        assert np.max(np.abs(wrong - dft2(psi_d) / math.sqrt(n))) > 1e-2
+
+
+def _probe_spectrum_at_origin(spec, e, alpha, df, cs):
+    beam = SimpleNamespace(probe=True, energy_ev=e, alpha_rad=alpha, defocus_a=df, cs_a=cs,
+                           probe_xy=np.array([[0.0, 0.0]]))
+    a = dft2(ms.initial_waves(spec, beam)[0])
+    kx = np.fft.fftfreq(spec.nx, d=spec.lx / spec.nx)
+    ky = np.fft.fftfreq(spec.ny, d=spec.ly / spec.ny)
+    return a, kx, ky
+
+
+def test_probe_aberration_phase_matches_the_angle_form():
+    # textbook aberration function in terms of the scattering angle theta = lambda |k|:
+    # chi(theta) = (2 pi / lambda) (Cs theta^4 / 4 + df theta^2 / 2); the probe's spectrum at the
+    # origin is A(k) exp(-i chi) times a positive constant.  Checked with Cs = 1.2 mm and 0.5 mm.
+    spec = _spec(128, 128, 48.0, 48.0, [1.0], bandlimit=0.0)
+    for e, alpha, df, cs in ((100e3, 0.025, -50.0, 1.2e7), (200e3, 0.02, 35.0, 5.0e6)):
+        lam = wavelength(e)
+        a, kx, ky = _probe_spectrum_at_origin(spec, e, alpha, df, cs)
+        assert a[0, 0].real > 0 and abs(a[0, 0].imag) < 1e-12 * a[0, 0].real
+        theta = lam * np.hypot(kx[None, :], ky[:, None])
+        inside = theta <= alpha
+        chi = (2 * math.pi / lam) * (cs * theta ** 4 / 4 + df * theta ** 2 / 2)
+        ratio = a / a[0, 0]
+        assert np.max(np.abs(ratio[inside] - np.exp(-1j * chi[inside]))) < 1e-9
+        assert np.max(np.abs(a[~inside])) < 1e-12
+        assert np.max(chi[inside]) > 20.0          # the Cs term is far from negligible here
+
+
+def test_spherical_aberration_shifts_the_focus_of_a_ring_by_cs_theta_squared():
+    # longitudinal spherical aberration: the part of the probe at angle theta behaves like a
+    # defocus df + Cs theta^2.  For two k points on neighbouring rings the phase difference
+    # divided by pi lambda (k2^2 - k1^2) is exactly df + Cs (theta1^2 + theta2^2) / 2 (the secant
+    # of a quadratic in k^2); phases are compared as small differences, so no unwrapping.
+    spec = _spec(128, 128, 48.0, 48.0, [1.0], bandlimit=0.0)
+    e, alpha, df, cs = 100e3, 0.025, -50.0, 1.2e7
+    lam = wavelength(e)
+    a, kx, ky = _probe_spectrum_at_origin(spec, e, alpha, df, cs)
+    checked = 0
+    for m in range(1, 20):
+        k1, k2 = kx[m] ** 2, kx[m] ** 2 + ky[1] ** 2
+        if lam * math.sqrt(k2) > alpha:
+            break
+        dphase = -np.angle(a[1, m] / a[0, m])
+        slope = dphase / (math.pi * lam * (k2 - k1))
+        assert abs(slope - (df + cs * lam ** 2 * (k1 + k2) / 2)) < 1e-6 * abs(cs * lam ** 2 * k2)
+        checked += 1
+    assert checked >= 10
