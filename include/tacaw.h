@@ -171,7 +171,10 @@ typedef struct {
 enum {
   TACAW_MODE_PLAIN = 0,    /* one snapshot per launch sequence: 2 launches per slice per snapshot */
   TACAW_MODE_BATCHED = 1   /* every wave of a grid class in one launch per slice and pass; the
-                              slice loop is captured once into a hipGraph and replayed */
+                              slice loop is captured into a hipGraph once per call structure
+                              (shapes, slice counts, band, schedule: not buffer addresses) and
+                              replayed; at most 32 graphs are kept per context (least recently
+                              used first out) */
 };
 
 /* ckpt_stride: 0 = no checkpoints; k > 0 stores the wave entering slices 0, k, 2k, ... (the state
@@ -233,8 +236,9 @@ int tacaw_periodogram_positions(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t 
                                 int32_t n_pos_used, int32_t n_e, int32_t hop, float* P_acc,
                                 int32_t accumulate, void* stream);
 
-/* Streamed segment periodograms for trajectories too long to keep every exit wave (Sec. II, the
- * averaging over segments of one long trajectory): exit waves arrive chunk by chunk in snapshot
+/* Streamed segment periodograms for trajectories too long to keep every exit wave (the paper's
+ * paragraph on averaging over segments of one long trajectory, after the two-step procedure,
+ * and the segment counts of its Si and Fe footnotes): exit waves arrive chunk by chunk in snapshot
  * order; the object keeps only the snapshots a not-yet-complete segment still needs (a window
  * of at most n_e + the largest chunk snapshots, in library-owned device memory), and adds each
  * segment's |Phi_g|^2 to P_acc as soon as its last snapshot has arrived.  Segments start at
@@ -279,7 +283,7 @@ int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int
                                      tacaw_c64* grad_exit, void* stream);
 
 /* ----------------------------------------------------------------------------------------------
- * Analysis outputs of the spectra (Sec. III, Figs. 1 and 2).  Every sum runs in a fixed order
+ * Analysis outputs of the spectra (the Si and hBN results paragraphs, Figs. 1 and 2).  Every sum runs in a fixed order
  * (float64, no atomics); maps are centred and cropped like the spectrum (index i holds the signed
  * frequency i - nq/2).  Asynchronous on `stream`; the library's workspace holds the per-q sums.
  * Errors: TACAW_E_ARG, TACAW_E_SIZE (n_e), TACAW_E_NOMEM, TACAW_E_HIP.
@@ -365,6 +369,20 @@ int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable);
  * Errors: TACAW_E_ARG (other values). */
 int tacaw_set_potential_precision(tacaw_ctx* ctx, int32_t split16);
 int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out);
+
+/* ----------------------------------------------------------------------------------------------
+ * Context caches.  A context keeps device copies of the small host tables its calls derive
+ * (propagator factors, band-limit and aperture tables, job tables, wave lists) keyed by content,
+ * and the captured graphs of batched multislice calls.  When a call starts while the tables exceed
+ * max_entries or max_bytes, the context waits for the device and drops every table and graph
+ * (they are rebuilt on demand); tables are never dropped during a call.  Graphs beyond max_graphs
+ * are dropped least recently used first, after their last replay has finished.
+ * Defaults: 4096 tables, 256 MiB, 32 graphs.  Values < 1 are rejected (TACAW_E_ARG).
+ * tacaw_cache_stats reports the current number of tables, their bytes and the number of graphs
+ * (host out pointers, each may be NULL). */
+int tacaw_set_cache_limits(tacaw_ctx* ctx, int64_t max_entries, int64_t max_bytes,
+                           int32_t max_graphs);
+int tacaw_cache_stats(tacaw_ctx* ctx, int64_t* n_tables, int64_t* table_bytes, int32_t* n_graphs);
 
 #ifdef __cplusplus
 }

@@ -106,6 +106,9 @@ _SIGS = {
     "tacaw_set_timing": ([_P, _I], ctypes.c_int),
     "tacaw_set_potential_precision": ([_P, _I], ctypes.c_int),
     "tacaw_get_timing": ([_P, ctypes.c_char_p, ctypes.POINTER(KernelStats)], ctypes.c_int),
+    "tacaw_set_cache_limits": ([_P, ctypes.c_int64, ctypes.c_int64, _I], ctypes.c_int),
+    "tacaw_cache_stats": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                           ctypes.POINTER(_I)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -446,3 +449,13 @@ def tacaw_get_timing(ctx, kind=None):
     st = KernelStats()
     _check(_lib.tacaw_get_timing(ctx.handle, kind.encode() if kind else None, ctypes.byref(st)))
     return dict(launches=st.launches, total_ms=st.total_ms, algo_bytes=st.algo_bytes)
+
+
+def tacaw_set_cache_limits(ctx, max_entries, max_bytes, max_graphs):
+    _check(_lib.tacaw_set_cache_limits(ctx.handle, int(max_entries), int(max_bytes), int(max_graphs)))
+
+
+def tacaw_cache_stats(ctx):
+    n, b, g = ctypes.c_int64(0), ctypes.c_int64(0), _I(0)
+    _check(_lib.tacaw_cache_stats(ctx.handle, ctypes.byref(n), ctypes.byref(b), ctypes.byref(g)))
+    return dict(tables=n.value, table_bytes=b.value, graphs=g.value)

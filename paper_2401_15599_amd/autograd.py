@@ -23,7 +23,9 @@ class TacawPotentials(torch.autograd.Function):
         ctx_ = context(xyz.device.index or 0)
         T = xyz.shape[0]
         V = torch.empty((T, spec.n_slices, spec.ny, spec.nx), dtype=torch.float32, device=xyz.device)
-        tacaw_build_potentials(ctx_, spec, xyz.contiguous(), species, ff, V)
+        xyz = xyz.contiguous()
+        species = species.contiguous()
+        tacaw_build_potentials(ctx_, spec, xyz, species, ff, V)
         ctx.save_for_backward(xyz, species)
         ctx.spec, ctx.ff = spec, ff
         return V

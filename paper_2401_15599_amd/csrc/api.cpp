@@ -200,11 +200,29 @@ struct tacaw_ctx {
   int max_lds = 65536;
   int n_cu = 256;
   std::map<std::string, DevBuf> ws;
+  // content-addressed device copies of small host tables; trimmed only when an API call starts
+  // (never while a call holds pointers into it), once it exceeds either limit
   std::unordered_map<std::string, Cached> cache;
   size_t cache_bytes = 0;
-  std::unordered_map<std::string, hipGraphExec_t> graphs;
+  size_t cache_max_entries = 4096, cache_max_bytes = (size_t)256 << 20;
+  int depth = 0;                     // nesting of API calls in progress (entry points call others)
+  // captured batched slice loops, keyed by the structure of the call (shapes, slice counts, band,
+  // class lists, schedule); buffer addresses are read from the graph's own job table, which each
+  // replay refreshes, so calls on new tensors replay the same graph.  Least recently used
+  // entries beyond max_graphs are destroyed.
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    MsJobDev* jobs_dev = nullptr;    // job table the captured kernels read
+    size_t jobs_bytes = 0;
+    hipEvent_t done = nullptr;       // recorded after the last replay
+    unsigned long long last_use = 0;
+  };
+  std::unordered_map<std::string, GraphEntry> graphs;
+  unsigned long long use_clock = 0;
+  size_t max_graphs = 32;
   std::map<int, Sched> sched;
   hipStream_t cap_stream = nullptr;
+  hipStream_t up_stream = nullptr;   // table uploads (waited for before the call goes on)
   std::string desc;
   // opt-in timing instrumentation
   struct Timed {
@@ -220,7 +238,11 @@ struct tacaw_ctx {
   ~tacaw_ctx() {
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.second.exec);
+      (void)hipFree(g.second.jobs_dev);
+      (void)hipEventDestroy(g.second.done);
+    }
     for (auto& t : timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto& c : cache) {
@@ -228,6 +250,7 @@ struct tacaw_ctx {
       if (c.second.host) (void)hipHostFree(c.second.host);
     }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (up_stream) (void)hipStreamDestroy(up_stream);
   }
 };
 
@@ -284,29 +307,66 @@ template <class F> void timed_launch(tacaw_ctx* c, hipStream_t st, const char* k
   c->timed.push_back({kind, a, b, bytes});
 }
 
-// content-addressed copy of a small host table in device memory (pinned staging kept alive)
-void* upload(tacaw_ctx* c, const void* data, size_t bytes, hipStream_t st, const char* tag) {
+void destroy_graph(tacaw_ctx::GraphEntry& g) {
+  (void)hipGraphExecDestroy(g.exec);
+  (void)hipFree(g.jobs_dev);
+  (void)hipEventDestroy(g.done);
+  g = tacaw_ctx::GraphEntry{};
+}
+
+// drop every cached table and every captured graph (they hold table addresses); waits for the
+// device so that no queued kernel still reads them
+void evict_tables(tacaw_ctx* c) {
+  hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  for (auto& g : c->graphs) destroy_graph(g.second);
+  c->graphs.clear();
+  for (auto& e : c->cache) {
+    (void)hipFree(e.second.dev);
+    (void)hipHostFree(e.second.host);
+  }
+  c->cache.clear();
+  c->cache_bytes = 0;
+}
+
+// Every entry point holds one while it runs.  The outermost one trims the table cache before the
+// call uploads anything, so a pointer returned by upload() stays valid until the call returns.
+struct CallScope {
+  tacaw_ctx* c;
+  explicit CallScope(tacaw_ctx* c_) : c(c_) {
+    if (c->depth == 0 &&
+        (c->cache_bytes > c->cache_max_bytes || c->cache.size() > c->cache_max_entries))
+      evict_tables(c);
+    ++c->depth;
+  }
+  ~CallScope() { --c->depth; }
+  CallScope(const CallScope&) = delete;
+  CallScope& operator=(const CallScope&) = delete;
+};
+
+// Content-addressed copy of a small host table in device memory (pinned staging kept alive).
+// The copy runs on the library's upload stream and is waited for, so the table is resident
+// before any stream uses it; entries are never freed during an API call.
+void* upload(tacaw_ctx* c, const void* data, size_t bytes, hipStream_t, const char* tag) {
   std::string key(tag);
   key.append((const char*)data, bytes);
   auto it = c->cache.find(key);
   if (it != c->cache.end()) return it->second.dev;
-  if (c->cache_bytes > (256u << 20) || c->cache.size() > 4096) {
-    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
-    c->graphs.clear();
-    for (auto& e : c->cache) {
-      (void)hipFree(e.second.dev);
-      (void)hipHostFree(e.second.host);
-    }
-    c->cache.clear();
-    c->cache_bytes = 0;
-  }
   Cached e;
   e.bytes = bytes;
   hip_check(hipHostMalloc(&e.host, std::max<size_t>(bytes, 16), hipHostMallocDefault), "hipHostMalloc");
   std::memcpy(e.host, data, bytes);
-  hip_check(hipMalloc(&e.dev, std::max<size_t>(bytes, 16)), "hipMalloc");
-  hip_check(hipMemcpyAsync(e.dev, e.host, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+  if (hipMalloc(&e.dev, std::max<size_t>(bytes, 16)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(e.host);
+    fail(TACAW_E_NOMEM, std::string("device table '") + tag + "'");
+  }
+  hipError_t err = hipMemcpyAsync(e.dev, e.host, bytes, hipMemcpyHostToDevice, c->up_stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(c->up_stream);
+  if (err != hipSuccess) {
+    (void)hipFree(e.dev);
+    (void)hipHostFree(e.host);
+    hip_check(err, "table upload");
+  }
   c->cache.emplace(key, e);
   c->cache_bytes += bytes;
   return e.dev;
@@ -404,6 +464,7 @@ struct ClassPlan {
   int Smax = 0;
   int kxb = 0;                     // widest band of the class's jobs (kx index)
   int kyb = 0;                     // largest |ky index| any column of the class's jobs keeps
+  int maxP = 0;                    // most waves per snapshot (probe positions) of the class's jobs
 };
 
 int active_prefix(const std::vector<int>& S_sorted_desc, int s) {
@@ -498,6 +559,7 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
     for (int t = 0; t < b.jobs[j].T; ++t) cp.groups.push_back(make_int2(j, t));
     cp.kxb = std::max(cp.kxb, b.jobs[j].kxb);
     cp.kyb = std::max(cp.kyb, kyb_of[j]);
+    cp.maxP = std::max(cp.maxP, b.jobs[j].P);
   }
   for (auto& cp : b.classes) {
     std::stable_sort(cp.groups.begin(), cp.groups.end(), [&](int2 a, int2 x) {
@@ -618,6 +680,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ra.band_in = s > 0 ? 1 : 0;   // the initial wave is not band-limited
         ra.band_out = 1;
         ra.prune = (s > 0 && plan_prunable(cp.nx, rs.row_plan, cp.kxb)) ? 1 : 0;
+        ra.single_pos = cp.maxP == 1 ? 1 : 0;
         L.row(cp.nx, rs, false, ra, active_prefix(wS, s), cp.kxb);
         const int n_mid = active_prefix(wS, s + 1), n_all = active_prefix(wS, s);
         ColArgs ca{};
@@ -668,17 +731,27 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
   }
 }
 
+// Key of a captured batched slice loop: everything that shapes its launches (per job: grid,
+// snapshots, positions, slices, band columns, checkpoint layout, illumination kind; per class:
+// the S-sorted lists, band extents and FFT schedule), but no buffer or table address: those
+// reach the kernels through the job table, which is copied into the graph's own table before
+// every replay.
 std::string graph_key(const MsBuild& b, int ckpt_stride, int mode, tacaw_ctx* c) {
-  std::string k((const char*)b.jobs.data(), b.jobs.size() * sizeof(MsJobDev));
-  k += "|" + std::to_string(ckpt_stride) + "|" + std::to_string(mode);
+  std::ostringstream k;
+  k << ckpt_stride << '|' << mode;
+  for (const MsJobDev& d : b.jobs)
+    k << "|j" << d.T << ',' << d.P << ',' << d.S << ',' << d.nx << ',' << d.ny << ',' << d.kxb << ','
+      << d.ck_stride << ',' << d.n_ck << ',' << (d.nap != nullptr);
+  std::string out = k.str();
   for (auto& cp : b.classes) {
-    Sched a = schedule_for(c, cp.nx), s2 = schedule_for(c, cp.ny);
-    k += "|" + std::to_string(cp.nx) + "," + std::to_string(a.row_plan) + "," +
-         std::to_string(s2.col_plan) + "," + std::to_string(s2.C) + "," +
-         std::to_string(s2.col_kind) + "," + std::to_string(s2.pp);
-    k.append((const char*)cp.groups.data(), cp.groups.size() * sizeof(int2));
+    Sched a = schedule_for(c, cp.nx), s2 = fit_cols(c, cp.ny, schedule_for(c, cp.ny), cp.nx);
+    out += "|c" + std::to_string(cp.nx) + "," + std::to_string(cp.ny) + "," +
+           std::to_string(cp.kxb) + "," + std::to_string(cp.kyb) + "," +
+           std::to_string(a.row_plan) + "," + std::to_string(s2.col_plan) + "," +
+           std::to_string(s2.C) + "," + std::to_string(s2.col_kind) + "," + std::to_string(s2.pp);
+    out.append((const char*)cp.groups.data(), cp.groups.size() * sizeof(int2));
   }
-  return k;
+  return out;
 }
 
 }  // namespace
@@ -708,6 +781,7 @@ int tacaw_create(int hip_device, tacaw_ctx** out) {
         lds > 0)
       c->max_lds = lds;
     hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking), "hipStreamCreate");
     prepare_dynamic_lds(c->max_lds);
     const char* tc = std::getenv("TACAW_TUNE_CACHE");
     if (tc && *tc) tacaw_load_tuning(c.get(), tc);
@@ -752,6 +826,7 @@ int tacaw_bin_atoms(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n_snap, 
                     int32_t* order, int32_t* n_outside, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_atoms(spec, n_snap, n_atoms, xyz, species, n_species);
     if (!offsets || !order) fail(TACAW_E_ARG, "null outputs");
     hipStream_t st = (hipStream_t)stream;
@@ -804,6 +879,7 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
                            void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_atoms(spec, n_snap, n_atoms, xyz, species, n_species);
     if (!ff || !V) fail(TACAW_E_ARG, "null form factors or output");
     for (int i = 0; i < 12 * n_species; ++i)
@@ -879,6 +955,7 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
                                     float* grad_xy, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_atoms(spec, n_snap, n_atoms, xyz, species, n_species);
     if (!ff || !grad_V || !grad_xy) fail(TACAW_E_ARG, "null form factors or gradient buffers");
     hipStream_t st = (hipStream_t)stream;
@@ -950,6 +1027,7 @@ int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, i
                      int32_t mode, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     if (mode != TACAW_MODE_PLAIN && mode != TACAW_MODE_BATCHED) fail(TACAW_E_ARG, "unknown mode");
     hipStream_t st = (hipStream_t)stream;
     MsBuild b = build_ms(ctx, n_jobs, jobs, ckpt_stride, st, false, nullptr, nullptr);
@@ -959,6 +1037,7 @@ int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, i
       return;
     }
     const std::string key = graph_key(b, ckpt_stride, mode, ctx);
+    const size_t jbytes = b.jobs.size() * sizeof(MsJobDev);
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
       // lists must be resident before capture (uploads are not captured)
@@ -968,25 +1047,59 @@ int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, i
         if (!cp.plane_waves.empty()) upload_vec(ctx, cp.plane_waves, st, "pw");
         if (!cp.probe_waves.empty()) upload_vec(ctx, cp.probe_waves, st, "pr");
       }
-      hipGraph_t g = nullptr;
-      hip_check(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
-                "hipStreamBeginCapture");
-      try {
-        run_forward(ctx, b, ckpt_stride, mode, ctx->cap_stream);
-      } catch (...) {
-        hipGraph_t dummy = nullptr;
-        (void)hipStreamEndCapture(ctx->cap_stream, &dummy);
-        if (dummy) (void)hipGraphDestroy(dummy);
-        throw;
+      if (ctx->graphs.size() >= ctx->max_graphs) {
+        auto lru = ctx->graphs.begin();
+        for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
+          if (g->second.last_use < lru->second.last_use) lru = g;
+        hip_check(hipEventSynchronize(lru->second.done), "hipEventSynchronize");
+        destroy_graph(lru->second);
+        ctx->graphs.erase(lru);
       }
-      hip_check(hipStreamEndCapture(ctx->cap_stream, &g), "hipStreamEndCapture");
-      hipGraphExec_t ex = nullptr;
-      hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      hip_check(e, "hipGraphInstantiate");
-      it = ctx->graphs.emplace(key, ex).first;
+      tacaw_ctx::GraphEntry e;
+      e.jobs_bytes = jbytes;
+      if (hipMalloc(&e.jobs_dev, jbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(TACAW_E_NOMEM, "graph job table");
+      }
+      hipError_t er = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
+      if (er == hipSuccess) er = hipEventRecord(e.done, st);
+      if (er != hipSuccess) {
+        (void)hipFree(e.jobs_dev);
+        if (e.done) (void)hipEventDestroy(e.done);
+        hip_check(er, "graph event");
+      }
+      MsBuild cb = b;
+      cb.jobs_dev = e.jobs_dev;
+      hipGraph_t g = nullptr;
+      er = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (er == hipSuccess) {
+        try {
+          run_forward(ctx, cb, ckpt_stride, mode, ctx->cap_stream);
+        } catch (...) {
+          hipGraph_t dummy = nullptr;
+          (void)hipStreamEndCapture(ctx->cap_stream, &dummy);
+          if (dummy) (void)hipGraphDestroy(dummy);
+          destroy_graph(e);
+          throw;
+        }
+        er = hipStreamEndCapture(ctx->cap_stream, &g);
+      }
+      if (er == hipSuccess) er = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (er != hipSuccess) {
+        destroy_graph(e);
+        hip_check(er, "graph capture");
+      }
+      it = ctx->graphs.emplace(key, e).first;
     }
-    hip_check(hipGraphLaunch(it->second, st), "hipGraphLaunch");
+    tacaw_ctx::GraphEntry& e = it->second;
+    e.last_use = ++ctx->use_clock;
+    // the previous replay (on any stream) has read the table before it is rewritten
+    hip_check(hipStreamWaitEvent(st, e.done, 0), "hipStreamWaitEvent");
+    hip_check(hipMemcpyAsync(e.jobs_dev, b.jobs_dev, jbytes, hipMemcpyDeviceToDevice, st),
+              "job table copy");
+    hip_check(hipGraphLaunch(e.exec, st), "hipGraphLaunch");
+    hip_check(hipEventRecord(e.done, st), "hipEventRecord");
   });
 }
 
@@ -995,6 +1108,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
                              float* const* grad_V, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     if (ckpt_stride < 1) fail(TACAW_E_ARG, "the adjoint needs the forward checkpoints (stride >= 1)");
     hipStream_t st = (hipStream_t)stream;
     MsBuild b = build_ms(ctx, n_jobs, jobs, ckpt_stride, st, true, grad_exit, grad_V);
@@ -1064,6 +1178,7 @@ int tacaw_multislice_adjoint(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job*
             ra.band_in = s > 0 ? 1 : 0;
             ra.band_out = 1;
             ra.prune = (s > 0 && plan_prunable(cp.nx, rs.row_plan, cp.kxb)) ? 1 : 0;
+            ra.single_pos = cp.maxP == 1 ? 1 : 0;
             L.row(cp.nx, rs, false, ra, nw, cp.kxb);
             if (s < s1 - 1) {
               ColArgs fa = ca;
@@ -1126,6 +1241,7 @@ int tacaw_periodogram_positions(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t 
                                 int32_t accumulate, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_spectrum(nx, ny, n_snap, n_pos, exit, n_e, hop);
     if (!P_acc) fail(TACAW_E_ARG, "null P_acc");
     if (pos0 < 0 || n_pos_used < 1 || (long)pos0 + n_pos_used > n_pos)
@@ -1155,6 +1271,7 @@ int tacaw_periodogram(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, in
                       int32_t accumulate, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_spectrum(nx, ny, n_snap, n_pos, exit, n_e, hop);
     if (!P_acc) fail(TACAW_E_ARG, "null P_acc");
     SpecArgs a{};
@@ -1188,6 +1305,7 @@ int tacaw_spectrum_finalize(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float*
                             const tacaw_spectrum_opts* opts, float* S, double* norm, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_opts(opts, nx, ny);
     if (!pow2_in(opts->n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
     if (!P_acc || !S) fail(TACAW_E_ARG, "null buffers");
@@ -1216,6 +1334,7 @@ int tacaw_autocorr_spectrum(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_sn
                             double* norm, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_opts(opts, nx, ny);
     validate_spectrum(nx, ny, n_snap, n_pos, exit, opts->n_e, opts->hop);
     if (!S) fail(TACAW_E_ARG, "null S");
@@ -1234,6 +1353,7 @@ int tacaw_autocorr_spectrum_backward(tacaw_ctx* ctx, int32_t nx, int32_t ny, int
                                      tacaw_c64* grad_exit, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_opts(opts, nx, ny);
     validate_spectrum(nx, ny, n_snap, n_pos, exit, opts->n_e, opts->hop);
     if (!S || !norm || !grad_S || !grad_exit) fail(TACAW_E_ARG, "null buffers");
@@ -1289,6 +1409,7 @@ int tacaw_segstream_create(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_pos
                            int32_t hop, float* P_acc, tacaw_segstream** out) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     if (!out) fail(TACAW_E_ARG, "out is NULL");
     *out = nullptr;
     if (!grid_size_ok(nx) || !grid_size_ok(ny)) fail(TACAW_E_SIZE, "grid size");
@@ -1407,6 +1528,7 @@ int tacaw_energy_integrals(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* 
                            void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_opts(opts, nx, ny);
     validate_crop(nx, ny, opts->nqx_out, opts->nqy_out);
     if (!pow2_in(opts->n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
@@ -1434,6 +1556,7 @@ int tacaw_qep_pattern(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, in
                       int32_t nqx_out, int32_t nqy_out, float* out, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     validate_crop(nx, ny, nqx_out, nqy_out);
     if (n_snap < 1 || n_pos < 1 || !exit || !out) fail(TACAW_E_ARG, "bad exit stack or output");
     if (t0 < 0 || t_stride < 1 || t_count < 1 || (long)t0 + (long)(t_count - 1) * t_stride >= n_snap)
@@ -1453,6 +1576,7 @@ int tacaw_relative_difference(tacaw_ctx* ctx, int32_t nqx, int32_t nqy, const fl
                               const float* B, float* out_row, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     if (nqx < 1 || nqy < 1 || !A || !B || !out_row) fail(TACAW_E_ARG, "bad maps or output");
     hip_check(launch_rel_diff_row(A, B, nqx, nqy, out_row, (hipStream_t)stream), "profile");
   });
@@ -1463,6 +1587,7 @@ int tacaw_path_cut(tacaw_ctx* ctx, double lx, double ly, int32_t nqx, int32_t nq
                    float* out, void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     if (!(lx > 0) || !(ly > 0)) fail(TACAW_E_ARG, "cell lengths must be positive");
     if (nqx < 1 || nqy < 1 || n_e < 1 || !S || !out) fail(TACAW_E_ARG, "bad spectrum or output");
     if (n_vert < 2 || !vertices || n_per_seg < 1) fail(TACAW_E_ARG, "need >= 2 vertices and >= 1 point per segment");
@@ -1492,6 +1617,7 @@ int tacaw_path_cut(tacaw_ctx* ctx, double lx, double ly, int32_t nqx, int32_t nq
 int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     ctx->timing = enable != 0;
   });
 }
@@ -1507,6 +1633,7 @@ int tacaw_set_potential_precision(tacaw_ctx* ctx, int32_t split16) {
 int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     if (!out) fail(TACAW_E_ARG, "null output");
     *out = tacaw_kernel_stats{0, 0.0, 0.0};
     std::vector<tacaw_ctx::Timed> keep;
@@ -1525,6 +1652,26 @@ int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out) 
       ctx->ev_pool.push_back(t.b);
     }
     ctx->timed.swap(keep);
+  });
+}
+
+int tacaw_set_cache_limits(tacaw_ctx* ctx, int64_t max_entries, int64_t max_bytes,
+                           int32_t max_graphs) {
+  return guarded([&] {
+    if (!ctx) fail(TACAW_E_ARG, "null context");
+    if (max_entries < 1 || max_bytes < 1 || max_graphs < 1) fail(TACAW_E_ARG, "cache limits must be >= 1");
+    ctx->cache_max_entries = (size_t)max_entries;
+    ctx->cache_max_bytes = (size_t)max_bytes;
+    ctx->max_graphs = (size_t)max_graphs;
+  });
+}
+
+int tacaw_cache_stats(tacaw_ctx* ctx, int64_t* n_tables, int64_t* table_bytes, int32_t* n_graphs) {
+  return guarded([&] {
+    if (!ctx) fail(TACAW_E_ARG, "null context");
+    if (n_tables) *n_tables = (int64_t)ctx->cache.size();
+    if (table_bytes) *table_bytes = (int64_t)ctx->cache_bytes;
+    if (n_graphs) *n_graphs = (int32_t)ctx->graphs.size();
   });
 }
 
@@ -1581,6 +1728,7 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
                    void* stream) {
   return guarded([&] {
     use_device(ctx);
+    CallScope scope(ctx);
     if (!grid_size_ok(n)) fail(TACAW_E_SIZE, "grid must be a power of two in [16, 1024], 560 or 1000");
     if (n_waves < 1) fail(TACAW_E_ARG, "n_waves must be >= 1");
     hipStream_t st = (hipStream_t)stream;
@@ -1629,6 +1777,7 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
         ra.stash_slot = -1;
         ra.write_out = 1;
         ra.ny = n;
+        ra.single_pos = 1;
         L.row(n, sc, false, ra, (long)cp.waves.size(), n / 2);
       });
       if (std::getenv("TACAW_TUNE_VERBOSE"))

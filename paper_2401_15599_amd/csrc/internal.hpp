@@ -57,6 +57,8 @@ struct RowArgs {
   int prune;               // band_in and band_out hold and the band leaves out the two middle
                            // registers of the plan (kx index N/2 - L .. N/2 + L - 1) in every job:
                            // the transforms skip them (forward kernel, plans with E >= 8)
+  int single_pos;          // every job of the launch has one wave per snapshot (P = 1): the
+                           // forward kernel evaluates the transmission where it applies it
 };
 
 struct ColArgs {

@@ -140,18 +140,39 @@ __device__ __forceinline__ void col_task(const ColArgs& a, int task, int tpw, in
 // the adjoint x pass, which holds three line-sized arrays); their transforms would otherwise take
 // every register for instruction-level parallelism.
 template <class P, bool ADJ = false> constexpr int min_waves() { return P::POW2 ? 1 : (ADJ ? 2 : 3); }
+// x pass: E = 16 power-of-two plans (1024 points) are held to 3 wavefronts per SIMD (their LDS
+// allows 3 workgroups per CU; measured 3.4 -> 4.0 TB/s at 1024^2 against the unconstrained
+// allocation at 2 per SIMD); forcing more than the natural 4 on E = 8 plans spills and is slower.
+template <class P, bool ADJ = false> constexpr int row_min_waves() {
+  return P::POW2 ? (ADJ ? 1 : (P::E <= 8 ? 1 : 3)) : (ADJ ? 2 : 3);
+}
 
 // ------------------------------------------------------------------------------------------------
 // x pass
-template <class P, bool ADJ, bool PR = false>
-__global__ __launch_bounds__(kThreads, (min_waves<P, ADJ>())) void k_row(RowArgs a) {
+// Power-of-two plans read their per-lane twiddles from one LDS table per workgroup, laid out
+// [k][L] (a line's lanes read consecutive words), instead of holding them in registers.  ONE: every
+// job of the launch has a single wave per snapshot (plane waves, single probe positions), so the
+// transmission is not shared; the V row is held as floats through the inverse transform and
+// exp(i sigma V) is evaluated where it is applied (fewer live registers).
+template <class P, bool ADJ, bool PR = false, bool ONE = false>
+__global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(RowArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES;
+  static_assert(!(ADJ && ONE), "the adjoint x pass evaluates the transmission once per row");
   __shared__ float2 lds_all[kWaves * LINES * P::LDS_LINE];
+  __shared__ float2 twl[P::POW2 ? P::NTW * L : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = lane / L, l = lane % L;
   float2* lds = lds_all + (wave * LINES + line) * P::LDS_LINE;
-  float2 tw[P::NTW];
-  PlanOps<P>::twiddles(tw, l);
+  if constexpr (P::POW2) {
+    if ((int)threadIdx.x < L) {
+      float2 t[P::NTW] = {};
+      PlanOps<P>::twiddles(t, threadIdx.x);
+#pragma unroll
+      for (int k = 0; k < P::NTW; ++k) twl[k * L + threadIdx.x] = t[k];
+    }
+    __syncthreads();
+  }
+  const TwStrided tw{twl + l, L};
   const float2* tab = fft_table_init<P>();
 
   // rows per image: a power of two (shift and mask) or any other length (division)
@@ -169,19 +190,25 @@ __global__ __launch_bounds__(kThreads, (min_waves<P, ADJ>())) void k_row(RowArgs
     const size_t row = (size_t)y * N;
     const GLOBAL_AS float* vrow = gp(J.V) + ((size_t)(t * J.S + s) * ny) * N + row;
     const float sigma = J.sigma;
-    float2 tr[E];
+    float vv[ONE ? E : 1];
+    float2 tr[ONE ? 1 : E];
+    if constexpr (ONE) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      float sn, cs;
-      sincos_phase(sigma * vrow[l + L * j], &sn, &cs);
-      tr[j] = make_float2(cs, sn);
+      for (int j = 0; j < E; ++j) vv[j] = vrow[l + L * j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        float sn, cs;
+        sincos_phase(sigma * vrow[l + L * j], &sn, &cs);
+        tr[j] = make_float2(cs, sn);
+      }
     }
     float gacc[ADJ ? E : 1];
     if constexpr (ADJ) {
 #pragma unroll
       for (int j = 0; j < E; ++j) gacc[j] = 0.f;
     }
-    const int P_ = J.P;
+    const int P_ = ONE ? 1 : J.P;
     // band: element x of a row (a kx column of W) outside the job's band is zero on input (not
     // read) and of no use on output (not written) when band_in / band_out say so
     const int kxb = J.kxb;
@@ -192,7 +219,7 @@ __global__ __launch_bounds__(kThreads, (min_waves<P, ADJ>())) void k_row(RowArgs
     for (int j = 0; j < E; ++j) inb |= (in_band(l + L * j, kxb, N) ? Mask(1) : Mask(0)) << j;
     const Mask rmask = a.band_in ? inb : ~Mask(0), wmask = a.band_out ? inb : ~Mask(0);
     for (int p = 0; p < P_; ++p) {
-      const int w = t * P_ + p;
+      const int w = t * J.P + p;
       float2 v[E];
       {
         const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s) + row;
@@ -213,8 +240,17 @@ __global__ __launch_bounds__(kThreads, (min_waves<P, ADJ>())) void k_row(RowArgs
 #pragma unroll
           for (int j = 0; j < E; ++j) st[l + L * j] = v[j];
         }
+        if constexpr (ONE) {
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = cmul(v[j], tr[j]);
+          for (int j = 0; j < E; ++j) {
+            float sn, cs;
+            sincos_phase(sigma * vv[j], &sn, &cs);
+            v[j] = cmul(v[j], make_float2(cs, sn));
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < E; ++j) v[j] = cmul(v[j], tr[j]);
+        }
       } else {
         // v = chi_s (adjoint at the post-transmission point); psi_s from the stash
         const GLOBAL_AS float2* st = gp(J.stash) + img_off(w * J.stash_k + a.stash_slot, N, ny) + row;
@@ -722,14 +758,19 @@ hipError_t launch_row(int n, int plan, bool adj, const RowArgs& a, int grid, hip
     if (adj) {
       hipLaunchKernelGGL((k_row<P, true>), dim3(grid), dim3(kThreads), 0, st, a);
     } else {
-      bool done = false;
-      if constexpr (P::E >= 8 && P::POW2) {
-        if (a.prune) {
-          hipLaunchKernelGGL((k_row<P, false, true>), dim3(grid), dim3(kThreads), 0, st, a);
-          done = true;
+      auto go = [&](auto one) {
+        constexpr bool ONE = decltype(one)::value;
+        bool done = false;
+        if constexpr (P::E >= 8 && P::POW2) {
+          if (a.prune) {
+            hipLaunchKernelGGL((k_row<P, false, true, ONE>), dim3(grid), dim3(kThreads), 0, st, a);
+            done = true;
+          }
         }
-      }
-      if (!done) hipLaunchKernelGGL((k_row<P, false>), dim3(grid), dim3(kThreads), 0, st, a);
+        if (!done) hipLaunchKernelGGL((k_row<P, false, false, ONE>), dim3(grid), dim3(kThreads), 0, st, a);
+      };
+      if (a.single_pos) go(std::true_type{});
+      else go(std::false_type{});
     }
     e = hipGetLastError();
   });

@@ -102,12 +102,13 @@ def test_multislice_plane_wave_odd_grid(n, mode):
     check(got, ref, 1e-4, f"{n} plane wave")
 
 
-@pytest.mark.parametrize("nx,ny", [(560, 560), (560, 128), (128, 1000)])
-def test_multislice_probe_odd_grid(nx, ny):
+@pytest.mark.parametrize("nx,ny,df,cs", [(560, 560, 20.0, 0.0), (560, 128, 20.0, 0.0),
+                                          (128, 1000, 20.0, 0.0), (560, 560, -40.0, 1.2e7)])
+def test_multislice_probe_odd_grid(nx, ny, df, cs):
     spec, pos, sp = _specimen(nx, ny, nx * 0.09, ny * 0.09, [2.0, 2.0], 200, 2, 52)
     V, _ = o_pot.potentials(pos, sp, form_factor_table(["A", "B"]), spec)
     V32 = V.astype(np.float32)
-    beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.030, defocus_a=20.0, cs_a=0.0,
+    beam = SimpleNamespace(probe=True, energy_ev=100e3, alpha_rad=0.030, defocus_a=df, cs_a=cs,
                            probe_xy=np.array([[nx * 0.045, ny * 0.045], [3.3, 4.1]]))
     got = _exit(spec, beam, V32)
     ref = o_ms.exit_waves(V32.astype(np.float64), spec, beam)

@@ -307,6 +307,27 @@ def test_autotune_cache_round_trip(tmp_path):
     check(out.cpu().numpy(), o_ms.exit_waves(V32.astype(np.float64), spec, beam), 1e-4)
 
 
+@pytest.mark.parametrize("energy,alpha,df,cs", [(100e3, 0.025, -50.0, 1.2e7),
+                                                  (200e3, 0.02, 35.0, 5.0e6)])
+def test_probe_with_defocus_and_spherical_aberration(energy, alpha, df, cs):
+    # the aberration phase chi = pi lambda df k^2 + pi Cs lambda^3 k^4 / 2 at Cs = 1.2 mm and
+    # 0.5 mm (hundreds of radians at the aperture edge), through a four-slice specimen
+    spec, pos, species = _random_specimen(128, 128, 32.0, 32.0, [2.0] * 4, 60, 2, 31)
+    V, _ = o_pot.potentials(pos, species, form_factor_table(["A", "B"]), spec)
+    V32 = V.astype(np.float32)
+    beam = SimpleNamespace(probe=True, energy_ev=energy, alpha_rad=alpha, defocus_a=df, cs_a=cs,
+                           probe_xy=np.array([[10.0, 12.0], [20.5, 7.25]]))
+    ref = o_ms.exit_waves(V32.astype(np.float64), spec, beam)
+    for mode in (tw.MODE_BATCHED, tw.MODE_PLAIN):
+        out = torch.full((2, 2, 128, 128), float("nan"), dtype=torch.complex64, device=DEV)
+        tw.tacaw_multislice(ctx(), [tw.MsJob(tw.specimen_from(spec), tw.beam_from(beam),
+                                             _gpu(V32), out)], mode=mode)
+        got = out.cpu().numpy()
+        for t in range(2):
+            for p in range(2):
+                check(got[t, p], ref[t, p], 1e-4)
+
+
 def _band_problem(seed):
     """Two specimens of one 64 x 64 grid class with different cell widths (so different sets of
     band-limited columns) and a probe aperture wider than the band limit (the entrance waves have
