@@ -265,6 +265,18 @@ void tacaw_segstream_destroy(tacaw_segstream* s);
 int tacaw_spectrum_finalize(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* P_acc,
                             const tacaw_spectrum_opts* opts, float* S, double* norm, void* stream);
 
+/* tacaw_spectrum_finalize without any allocation, for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops): the same kernels, with the partial sums of
+ * Z and the Kubo table (computed on the device) in a fixed 16 KiB scratch array that the library
+ * holds once per GPU for the life of the process.  Supports every n_e of tacaw_spectrum_finalize
+ * (<= 1024).  Calls no hipMalloc/hipFree, uploads no table and never trims the context caches.
+ * Every call on one GPU uses that GPU's one scratch array: calls that overlap on one GPU (other
+ * streams, other threads, other contexts) race and must be serialised by the caller.
+ * Arguments, outputs and errors as tacaw_spectrum_finalize (TACAW_E_SIZE if n_e would not fit). */
+int tacaw_spectrum_finalize_noalloc(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* P_acc,
+                                    const tacaw_spectrum_opts* opts, float* S, double* norm,
+                                    void* stream);
+
 /* tacaw_periodogram (accumulate = 0) followed by tacaw_spectrum_finalize; P_acc lives in the
  * workspace. */
 int tacaw_autocorr_spectrum(tacaw_ctx* ctx, int32_t nx, int32_t ny, int32_t n_snap, int32_t n_pos,

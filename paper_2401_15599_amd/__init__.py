@@ -90,6 +90,8 @@ _SIGS = {
     "tacaw_segstream_window": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], ctypes.c_int),
     "tacaw_segstream_destroy": ([_P], None),
     "tacaw_spectrum_finalize": ([_P, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P, _P], ctypes.c_int),
+    "tacaw_spectrum_finalize_noalloc": ([_P, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P, _P],
+                                        ctypes.c_int),
     "tacaw_autocorr_spectrum": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P, _P],
                                 ctypes.c_int),
     "tacaw_autocorr_spectrum_backward": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_Opts), _P, _P,
@@ -371,6 +373,13 @@ def tacaw_spectrum_finalize(ctx, P_acc, opts, S, norm=None, stream=None):
     o = opts.c()
     _check(_lib.tacaw_spectrum_finalize(ctx.handle, nx, ny, _ptr(P_acc), ctypes.byref(o), _ptr(S),
                                         _ptr(norm), _stream(stream)))
+
+
+def tacaw_spectrum_finalize_noalloc(ctx, P_acc, opts, S, norm=None, stream=None):
+    _, ny, nx = P_acc.shape
+    o = opts.c()
+    _check(_lib.tacaw_spectrum_finalize_noalloc(ctx.handle, nx, ny, _ptr(P_acc), ctypes.byref(o),
+                                                _ptr(S), _ptr(norm), _stream(stream)))
 
 
 def tacaw_autocorr_spectrum(ctx, exit, opts, S, norm=None, stream=None):

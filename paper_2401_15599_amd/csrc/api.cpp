@@ -34,6 +34,16 @@ void prepare_dynamic_lds(int max_bytes);
 
 using namespace tacaw;
 
+// Scratch memory of tacaw_spectrum_finalize_noalloc (partial sums of the normalisation and the
+// Kubo table), one copy per GPU, held until the process ends.  In host code this name is not a
+// device address: the context keeps the address hipGetSymbolAddress returns for its device.
+namespace {
+constexpr int kNoallocParts = 512;                     // partial sums of Z
+constexpr size_t kNoallocKuboOff = 4352;               // (kNoallocParts + 2) doubles, rounded up
+constexpr size_t kScratchBytes = 16384;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 // ------------------------------------------------------------------------------------------------
 // errors
 static thread_local std::string g_err;
@@ -223,6 +233,7 @@ struct tacaw_ctx {
   std::map<int, Sched> sched;
   hipStream_t cap_stream = nullptr;
   hipStream_t up_stream = nullptr;   // table uploads (waited for before the call goes on)
+  unsigned char* scratch_dev = nullptr;   // this device's copy of `scratch`
   std::string desc;
   // opt-in timing instrumentation
   struct Timed {
@@ -782,6 +793,9 @@ int tacaw_create(int hip_device, tacaw_ctx** out) {
       c->max_lds = lds;
     hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     hip_check(hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking), "hipStreamCreate");
+    void* sp = nullptr;
+    hip_check(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    c->scratch_dev = (unsigned char*)sp;
     prepare_dynamic_lds(c->max_lds);
     const char* tc = std::getenv("TACAW_TUNE_CACHE");
     if (tc && *tc) tacaw_load_tuning(c.get(), tc);
@@ -1320,6 +1334,41 @@ int tacaw_spectrum_finalize(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float*
     double* part = (double*)workspace(ctx, "partial", (a.n_part + 2) * sizeof(double));
     a.partial = part;
     a.norm = norm ? norm : part + a.n_part;
+    a.n_e = opts->n_e;
+    a.nx = nx;
+    a.ny = ny;
+    a.nqx = opts->nqx_out;
+    a.nqy = opts->nqy_out;
+    hip_check(launch_finalize(a, st), "finalize kernels");
+  });
+}
+
+int tacaw_spectrum_finalize_noalloc(tacaw_ctx* ctx, int32_t nx, int32_t ny, const float* P_acc,
+                                    const tacaw_spectrum_opts* opts, float* S, double* norm,
+                                    void* stream) {
+  return guarded([&] {
+    // no CallScope: it may drop cached tables (hipFree); nothing here allocates or frees
+    use_device(ctx);
+    validate_opts(opts, nx, ny);
+    if (!pow2_in(opts->n_e, 16, 1024)) fail(TACAW_E_SIZE, "n_e must be a power of two in [16, 1024]");
+    if (!P_acc || !S) fail(TACAW_E_ARG, "null buffers");
+    if (kNoallocKuboOff + (size_t)opts->n_e * sizeof(float) > kScratchBytes ||
+        (size_t)(kNoallocParts + 2) * sizeof(double) > kNoallocKuboOff)
+      fail(TACAW_E_SIZE, "n_e = " + std::to_string(opts->n_e) + " does not fit the " +
+                             std::to_string(kScratchBytes) + "-byte scratch");
+    if (!ctx->scratch_dev) fail(TACAW_E_STATE, "no scratch address for this device");
+    hipStream_t st = (hipStream_t)stream;
+    double* part = (double*)ctx->scratch_dev;
+    float* K = (float*)(ctx->scratch_dev + kNoallocKuboOff);
+    hip_check(launch_kubo_fill(K, opts->n_e, opts->dt_fs, 1.0 / (kKb * opts->temperature_k), st),
+              "Kubo table");
+    FinArgs a{};
+    a.P = P_acc;
+    a.K = K;
+    a.S = S;
+    a.n_part = kNoallocParts;
+    a.partial = part;
+    a.norm = norm ? norm : part + kNoallocParts;
     a.n_e = opts->n_e;
     a.nx = nx;
     a.ny = ny;

@@ -178,6 +178,7 @@ struct FinArgs {
   int n_e, nx, ny, nqx, nqy, n_part;
 };
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st);
+hipError_t launch_kubo_fill(float* K, int n_e, double dt_fs, double beta, hipStream_t st);
 
 // analysis outputs (patterns, line profiles, dispersion cuts)
 hipError_t launch_energy_sums(const float* P, const float* K, int n_e, long nq, double* sp,

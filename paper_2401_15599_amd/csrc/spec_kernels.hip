@@ -167,6 +167,25 @@ __global__ __launch_bounds__(256) void k_fin_write(FinArgs a) {
   }
 }
 
+// Kubo factors in DFT order computed on the device, in the host's float64 order of operations:
+// E_k = 2 pi hbar k' / (n_e dt), x = beta E_k, K = 1 + x/2 + x^2/12 for |x| < 1e-4, else
+// x / (-expm1(-x)) (eq:kubo_vs_normal)
+__global__ __launch_bounds__(256) void k_kubo_fill(float* K, int n_e, double dt_fs, double beta) {
+  const double two_pi_hbar = 2.0 * 3.14159265358979323846 * 0.6582119569;
+  for (int i = (int)threadIdx.x; i < n_e; i += 256) {
+    const int kp = i < n_e / 2 ? i : i - n_e;
+    const double e = two_pi_hbar * (double)kp / ((double)n_e * dt_fs);
+    const double x = beta * e;
+    const double k = fabs(x) < 1e-4 ? 1.0 + x / 2.0 + x * x / 12.0 : x / (-expm1(-x));
+    K[i] = (float)k;
+  }
+}
+
+hipError_t launch_kubo_fill(float* K, int n_e, double dt_fs, double beta, hipStream_t st) {
+  hipLaunchKernelGGL(k_kubo_fill, dim3(1), dim3(256), 0, st, K, n_e, dt_fs, beta);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const FinArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_partial, dim3(a.n_part), dim3(kRedThreads), 0, st, a);
   hipLaunchKernelGGL(k_fin_total, dim3(1), dim3(kRedThreads), 0, st, a.partial, a.n_part, a.norm);
