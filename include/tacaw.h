@@ -170,11 +170,17 @@ typedef struct {
 
 enum {
   TACAW_MODE_PLAIN = 0,    /* one snapshot per launch sequence: 2 launches per slice per snapshot */
-  TACAW_MODE_BATCHED = 1   /* every wave of a grid class in one launch per slice and pass; the
+  TACAW_MODE_BATCHED = 1,  /* every wave of a grid class in one launch per slice and pass; the
                               slice loop is captured into a hipGraph once per call structure
                               (shapes, slice counts, band, schedule: not buffer addresses) and
                               replayed; at most 32 graphs are kept per context (least recently
                               used first out) */
+  TACAW_MODE_PERSISTENT = 2 /* as BATCHED, with the grid classes of a call as concurrent branches of
+                              the captured graph, and square classes of at most 128 points per
+                              axis run by one launch of persistent workgroups: each keeps a whole
+                              wave on its CU (registers and LDS) through all of that wave's
+                              slices, reading only V and writing the checkpoints and the exit
+                              wave, then takes the next wave of the class (any slice count) */
 };
 
 /* ckpt_stride: 0 = no checkpoints; k > 0 stores the wave entering slices 0, k, 2k, ... (the state

@@ -25,7 +25,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 PLANE_WAVE, PROBE = 0, 1
-MODE_PLAIN, MODE_BATCHED = 0, 1
+MODE_PLAIN, MODE_BATCHED, MODE_PERSISTENT = 0, 1, 2
 
 
 class TacawError(RuntimeError):

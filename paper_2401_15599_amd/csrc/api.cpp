@@ -234,6 +234,10 @@ struct tacaw_ctx {
   hipStream_t cap_stream = nullptr;
   hipStream_t up_stream = nullptr;   // table uploads (waited for before the call goes on)
   unsigned char* scratch_dev = nullptr;   // this device's copy of `scratch`
+  // side streams (default priority) of the persistent mode's concurrent grid classes
+  static constexpr size_t kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
   std::string desc;
   // opt-in timing instrumentation
   struct Timed {
@@ -262,6 +266,11 @@ struct tacaw_ctx {
     }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (up_stream) (void)hipStreamDestroy(up_stream);
+    for (auto& x : side)
+      if (x) (void)hipStreamDestroy(x);
+    for (auto& e : join_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
   }
 };
 
@@ -649,9 +658,20 @@ struct Launcher {
   }
 };
 
-void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipStream_t st) {
-  Launcher L{c, st};
-  for (const ClassPlan& cp : b.classes) {
+void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipStream_t st_main) {
+  // persistent mode: the grid classes run concurrently on the context's side streams, forked from
+  // and joined back into the caller's stream (inside a capture they become parallel branches)
+  const bool fork = mode == TACAW_MODE_PERSISTENT && b.classes.size() > 1;
+  const int n_side = fork ? (int)std::min<size_t>(b.classes.size(), tacaw_ctx::kSide) : 0;
+  if (fork) {
+    hip_check(hipEventRecord(c->fork_ev, st_main), "hipEventRecord");
+    for (int i = 0; i < n_side; ++i)
+      hip_check(hipStreamWaitEvent(c->side[i], c->fork_ev, 0), "hipStreamWaitEvent");
+  }
+  for (size_t ci = 0; ci < b.classes.size(); ++ci) {
+    const ClassPlan& cp = b.classes[ci];
+    const hipStream_t st = fork ? c->side[ci % n_side] : st_main;
+    Launcher L{c, st};
     const Sched rs = schedule_for(c, cp.nx);
     const Sched cs = fit_cols(c, cp.ny, schedule_for(c, cp.ny), cp.nx);
     // the staged init kernels use the same column count (their LDS tile is the smaller one)
@@ -722,7 +742,46 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
     int4* waves_dev = upload_vec(c, cp.waves, st, "waves");
     int4* plane_dev = cp.plane_waves.empty() ? nullptr : upload_vec(c, cp.plane_waves, st, "pw");
     int4* probe_dev = cp.probe_waves.empty() ? nullptr : upload_vec(c, cp.probe_waves, st, "pr");
-    if (mode == TACAW_MODE_PLAIN) {
+    if (mode == TACAW_MODE_PERSISTENT && resident_ok(cp.nx, cp.ny)) {
+      // entrance waves by the init kernels, then one launch for every wave of the class: each
+      // workgroup keeps a wave on its CU through all of that wave's slices and then takes the next
+      {
+        ColArgs ia{};
+        ia.jobs = b.jobs_dev;
+        ia.out_buf = BUF_W;
+        ia.C = cs.C;
+        ia.nx = cp.nx;
+        if (!cp.plane_waves.empty()) {
+          ia.waves = plane_dev;
+          ia.n_waves = (int)cp.plane_waves.size();
+          long g = std::min<long>(ia.n_waves, (long)c->n_cu * 8);
+          hip_check(launch_plane_init(ia, (int)g, st), "plane-wave init");
+        }
+        if (!cp.probe_waves.empty()) {
+          ia.waves = probe_dev;
+          ia.n_waves = (int)cp.probe_waves.size();
+          long g = std::min<long>((long)ia.n_waves * (cp.nx / cs.C), (long)c->n_cu * 8);
+          hip_check(launch_probe_init(cp.ny, cs.col_plan, ia, (int)g, st), "probe init");
+        }
+      }
+      ColArgs ra{};
+      ra.jobs = b.jobs_dev;
+      ra.waves = waves_dev;
+      ra.n_waves = (int)cp.waves.size();
+      ra.scale = (float)(1.0 / ((double)cp.nx * cp.ny));
+      ra.nx = cp.nx;
+      const long g = std::min<long>(ra.n_waves, (long)c->n_cu * resident_workgroups_per_cu(cp.nx, c->max_lds));
+      // HBM bytes: V of every slice, the exit wave, the checkpoints
+      double bytes = 0.0;
+      const double img = (double)cp.nx * cp.ny;
+      for (const int4& w : cp.waves) {
+        const MsJobDev& d = b.jobs[w.x];
+        bytes += img * (4.0 * d.S + 16.0 + 8.0 * d.n_ck);   // + entrance wave read
+      }
+      timed_launch(c, st, "resident", bytes, [&] {
+        hip_check(launch_resident(cp.nx, ra, (int)std::max<long>(g, 1), st), "resident slice loop");
+      });
+    } else if (mode == TACAW_MODE_PLAIN) {
       // one snapshot (all its probe positions) per launch sequence
       size_t wi = 0;
       for (size_t gi = 0; gi < cp.groups.size(); ++gi) {
@@ -738,6 +797,12 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
     } else {
       do_range(groups_dev, (int)cp.groups.size(), waves_dev, cp.group_S, cp.wave_S, plane_dev,
                (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size());
+    }
+  }
+  if (fork) {
+    for (int i = 0; i < n_side; ++i) {
+      hip_check(hipEventRecord(c->join_ev[i], c->side[i]), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(st_main, c->join_ev[i], 0), "hipStreamWaitEvent");
     }
   }
 }
@@ -793,6 +858,9 @@ int tacaw_create(int hip_device, tacaw_ctx** out) {
       c->max_lds = lds;
     hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     hip_check(hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking), "hipStreamCreate");
+    for (auto& x : c->side) hip_check(hipStreamCreateWithFlags(&x, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "hipEventCreate");
+    for (auto& e : c->join_ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     void* sp = nullptr;
     hip_check(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
     c->scratch_dev = (unsigned char*)sp;
@@ -1042,7 +1110,8 @@ int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, i
   return guarded([&] {
     use_device(ctx);
     CallScope scope(ctx);
-    if (mode != TACAW_MODE_PLAIN && mode != TACAW_MODE_BATCHED) fail(TACAW_E_ARG, "unknown mode");
+    if (mode != TACAW_MODE_PLAIN && mode != TACAW_MODE_BATCHED && mode != TACAW_MODE_PERSISTENT)
+      fail(TACAW_E_ARG, "unknown mode");
     hipStream_t st = (hipStream_t)stream;
     MsBuild b = build_ms(ctx, n_jobs, jobs, ckpt_stride, st, false, nullptr, nullptr);
     b.jobs_dev = upload_vec(ctx, b.jobs, st, "jobs");

@@ -305,34 +305,37 @@ TACAW_HD void sincospi_f(float x, float* s, float* c) {
 #endif
 }
 
-// sin x and cos x for the transmission phase sigma V_s (moderate |x|).  Reduction by k = nearest
-// integer to x / (pi/2) with pi/2 split into three floats (Cody and Waite), each step one fused
-// multiply-add, then Taylor polynomials on |r| <= pi/4 (truncation below 2e-9) and the quadrant's
-// sign/swap.  Beyond |x| = 8192 the library routine is used.
+// sin x and cos x for the transmission phase sigma V_s.  Reduction by k = nearest integer to
+// x / (pi/2): for |x| <= 8192 with pi/2 split into three floats (Cody and Waite), each step one
+// fused multiply-add; beyond (never reached by physical potentials, kept exact for any input) in
+// float64 with pi/2 split into two doubles.  Then Taylor polynomials on |r| <= pi/4 (truncation
+// below 2e-9) and the quadrant's sign/swap.  NaN and infinite x give NaN.
 TACAW_HD void sincos_phase(float x, float* s, float* c) {
   constexpr double kHalfPi = 1.57079632679489661923;
   constexpr float P1 = (float)kHalfPi;
   constexpr float P2 = (float)(kHalfPi - (double)P1);
   constexpr float P3 = (float)(kHalfPi - (double)P1 - (double)P2);
-  if (!(fabsf(x) <= 8192.0f)) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    sincosf(x, s, c);
-#else
-    *s = (float)__builtin_sin((double)x);
-    *c = (float)__builtin_cos((double)x);
-#endif
-    return;
+  float r;
+  int q;
+  if (fabsf(x) <= 8192.0f) {
+    const float k = rintf(x * (float)(1.0 / kHalfPi));
+    r = fmaf(-k, P1, x);
+    r = fmaf(-k, P2, r);
+    r = fmaf(-k, P3, r);
+    q = (int)k & 3;
+  } else {
+    constexpr double D1 = 1.5707963267948966;          // pi/2 rounded to double
+    constexpr double D2 = 6.123233995736766e-17;       // pi/2 - D1
+    const double xd = (double)x;
+    const double kd = rint(xd * (1.0 / kHalfPi));
+    r = (float)fma(-kd, D2, fma(-kd, D1, xd));
+    q = (int)fmod(kd, 4.0) & 3;
   }
-  const float k = rintf(x * (float)(1.0 / kHalfPi));
-  float r = fmaf(-k, P1, x);
-  r = fmaf(-k, P2, r);
-  r = fmaf(-k, P3, r);
   const float r2 = r * r;
   const float sp = r + r * r2 * fmaf(r2, fmaf(r2, fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f),
                                                1.0f / 120.0f), -1.0f / 6.0f);
   const float cp = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f),
                                                    -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
-  const int q = (int)k & 3;
   const float ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
   *s = (q & 2) ? -ss : ss;
   *c = ((q + 1) & 2) ? -cc : cc;

@@ -122,6 +122,7 @@ static int check_sincos() {
   for (int k = -4000; k <= 4000; ++k)
     for (int d = -3; d <= 3; ++d) probe(std::nextafter((float)(k * M_PI_4), d > 0 ? 1e9f : -1e9f) + d * 1e-6f);
   for (int i = 0; i < 1000; ++i) probe(8000.0f + (float)i * 1.37f);             // both branches
+  for (int i = 0; i < 1400; ++i) probe((i & 1 ? -1.0f : 1.0f) * 1.0e4f * std::pow(1.013f, (float)i));  // to ~7e11
   const bool ok = worst < 1e-6;
   std::printf("%-28s max abs error %.2e  %s\n", "sincos_phase", worst, ok ? "ok" : "FAIL");
   return ok ? 0 : 1;

@@ -117,6 +117,11 @@ int col_wave_threads(int n, int plan, int C);
 int plan_lanes(int n, int plan);
 hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStream_t st);
 hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st);
+// resident slice loop of small square grids (whole wave per workgroup, every slice on the CU):
+// available grids, workgroups per CU, launch over a class's S-sorted wave list (a.scale = 1/(n n))
+bool resident_ok(int nx, int ny);
+int resident_workgroups_per_cu(int n, int max_lds);
+hipError_t launch_resident(int n, const ColArgs& a, int grid, hipStream_t st);
 int row_lines_per_wave(int n, int plan);
 int col_lds_bytes(int n, int plan, int C);
 // grid lengths with FFT plans; the root-table LDS of a plan; y-pass kinds a plan supports

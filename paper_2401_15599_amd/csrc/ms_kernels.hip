@@ -25,7 +25,7 @@ template <class F> static bool with_plan(int n, int idx, F&& f) {
     case 16: if (idx == 1) f(P16b{}); else f(P16a{}); return true;
     case 32: if (idx == 1) f(P32b{}); else f(P32a{}); return true;
     case 64: if (idx == 1) f(P64b{}); else f(P64a{}); return true;
-    case 128: if (idx == 1) f(P128b{}); else f(P128a{}); return true;
+    case 128: if (idx == 1) f(P128b{}); else if (idx == 2) f(P128c{}); else f(P128a{}); return true;
     case 256: if (idx == 1) f(P256b{}); else if (idx == 2) f(P256c{}); else f(P256a{}); return true;
     case 512: if (idx == 1) f(P512b{}); else f(P512a{}); return true;
     case 1024: if (idx == 1) f(P1024b{}); else f(P1024a{}); return true;
@@ -39,8 +39,8 @@ template <class F> static bool with_plan(int n, int idx, F&& f) {
 
 int n_plans(int n) {
   switch (n) {
-    case 16: case 32: case 64: case 128: case 512: case 1024: return 2;
-    case 256: return 3;
+    case 16: case 32: case 64: case 512: case 1024: return 2;
+    case 128: case 256: return 3;
     case 560: return 4;
     case 1000: return 2;
     default: return 0;
@@ -49,7 +49,8 @@ int n_plans(int n) {
 
 const char* plan_name(int n, int idx) {
   static const char* names[] = {"16:L2:8x2", "16:L4:4x4", "32:L4:8x4", "32:L2:16x2", "64:L8:8x8",
-                                "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "256:L32:8x8x4",
+                                "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "128:L8:8x4x4",
+                                "256:L32:8x8x4",
                                 "256:L16:16x16", "256:L64:4x4x4x4", "512:L64:8x8x8",
                                 "512:L32:16x8x4", "1024:L64:16x16x4", "1024:L64:16x4x16",
                                 "560:L28:4x5x4x7", "560:L56:2x5x2x2x14", "560:L28:20x4x7",
@@ -57,8 +58,8 @@ const char* plan_name(int n, int idx) {
   int base = 0;
   switch (n) {
     case 16: base = 0; break; case 32: base = 2; break; case 64: base = 4; break;
-    case 128: base = 6; break; case 256: base = 8; break; case 512: base = 11; break;
-    case 1024: base = 13; break; case 560: base = 15; break; case 1000: base = 19; break;
+    case 128: base = 6; break; case 256: base = 9; break; case 512: base = 12; break;
+    case 1024: base = 14; break; case 560: base = 16; break; case 1000: base = 20; break;
     default: return "?";
   }
   if (idx < 0 || idx >= n_plans(n)) return "?";
@@ -602,6 +603,122 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_probe_init(ColArgs
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Resident slice loop (small square grids).  One workgroup of N lines x L lanes holds a whole wave
+// in registers (E values per lane) and runs every slice of it on the CU: the x transforms in row
+// layout (thread (line, l) holds row y = line, x = l + L j), the y transforms in column layout
+// (column kx = line, y = l + L j), LDS transposes in between.  Per slice step the wave never
+// leaves the CU: HBM sees the V map of the slice, the checkpoints and, once, the exit wave.  The
+// workgroups are persistent: each takes waves wi = blockIdx.x, blockIdx.x + gridDim.x, ... of the
+// class's S-sorted wave list and runs each through its own job's slice count.
+template <class P> constexpr int res_line_stride() {
+  // exchange region of one line: padded positions 0 .. pad_of(N - 1), rounded up to an odd count
+  return ((P::N - 1 + (P::N - 1) / 8 + 1) | 1);
+}
+template <class P> constexpr int res_lds_words() {
+  constexpr int x = P::N * res_line_stride<P>(), t = P::N * (P::N + 1);
+  return (x > t ? x : t) + P::NTW * P::L;
+}
+template <class P> constexpr int max_radix() {
+  int m = 0;
+  for (int k = 0; k < P::NR; ++k) m = P::radix(k) > m ? P::radix(k) : m;
+  return m;
+}
+// one line per thread (N L <= 1024), radix at most 8 (the registers of a 1024-thread workgroup)
+template <class P> constexpr bool res_plan_ok() {
+  return P::POW2 && P::FULL && P::N <= 128 && P::N * P::L <= 1024 && max_radix<P>() <= 8 &&
+         res_lds_words<P>() * 8 <= 160 * 1024;
+}
+template <class P> constexpr int res_threads() { return P::N * P::L; }
+
+template <class P>
+__global__ __launch_bounds__(res_threads<P>()) void k_resident(ColArgs a) {
+  constexpr int N = P::N, L = P::L, E = P::E, XS = res_line_stride<P>(), TS = N + 1;
+  constexpr int TAB = (N * XS > N * TS ? N * XS : N * TS);
+  extern __shared__ float2 lds_mem[];
+  float2* twl = lds_mem + TAB;
+  const int tid = threadIdx.x, line = tid / L, l = tid % L;
+  if (tid < L) {
+    float2 t[P::NTW] = {};
+    PlanOps<P>::twiddles(t, tid);
+#pragma unroll
+    for (int k = 0; k < P::NTW; ++k) twl[k * L + tid] = t[k];
+  }
+  __syncthreads();
+  const TwStrided tw{twl + l, L};
+  float2* xl = lds_mem + line * XS;                // this line's exchange region
+  const float inv_n = a.scale;                     // 1 / (N N)
+  const int y = line, c = line;                    // row y (row layout) / column kx (column layout)
+  for (int wi = blockIdx.x; wi < a.n_waves; wi += gridDim.x) {
+    const int4 wv = const_at(a.waves, wi);
+    CJob& J = job_at(a.jobs, wv.x);
+    const int w = wv.y * J.P + wv.z, S = J.S, t = wv.y;
+    GLOBAL_AS float2* img = gp(J.W) + img_off(w, N, N);
+    // the entrance wave W(kx, y), written by the init kernels, in row layout
+    float2 v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = img[(size_t)y * N + l + L * j];
+    for (int s = 0; s < S; ++s) {
+      if (s > 0) {
+        // column layout -> row layout through the transpose table [y][kx]
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; ++j) lds_mem[(l + L * j) * TS + c] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = lds_mem[y * TS + l + L * j];
+        __syncthreads();
+      }
+      if (J.n_ck > 0 && s % J.ck_stride == 0) {
+        GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, N) + (size_t)y * N;
+#pragma unroll
+        for (int j = 0; j < E; ++j) ck[l + L * j] = v[j];
+      }
+      // x pass: psi = G_x W, u = exp(i sigma V_s) psi, W' = F_x u
+      FFT<P>::template run<true>(v, tw, xl, l);
+      {
+        const GLOBAL_AS float* vrow = gp(J.V) + ((size_t)(t * S + s) * N + y) * N;
+        const float sigma = J.sigma;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          float sn, csn;
+          sincos_phase(sigma * vrow[l + L * j], &sn, &csn);
+          v[j] = cmul(v[j], make_float2(csn, sn));
+        }
+      }
+      FFT<P>::template run<false>(v, tw, xl, l);
+      // row layout -> column layout
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < E; ++j) lds_mem[y * TS + l + L * j] = v[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = lds_mem[(l + L * j) * TS + c];
+      __syncthreads();
+      // y pass: F_y, band-limited propagator M P_s, then G_y (or the exit wave after the last slice)
+      FFT<P>::template run<false>(v, tw, xl, l);
+      const bool last = s == S - 1;
+      const int nm = gp(J.nmax)[c];
+      const float2 pxs = cscale(gp(J.px)[(size_t)s * N + c], last ? J.scale_last : inv_n);
+      const GLOBAL_AS float2* pys = gp(J.py) + (size_t)s * N;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int n = l + L * j;
+        const int ns = n < N / 2 ? n : n - N;
+        float2 d = cmul(pxs, pys[n]);
+        if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
+        v[j] = cmul(v[j], d);
+      }
+      if (last) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) img[(size_t)(l + L * j) * N + c] = v[j];
+      } else {
+        FFT<P>::template run<true>(v, tw, xl, l);
+      }
+    }
+  }
+}
+
 // plane wave: W(kx, y) = delta_{kx,0} / sqrt(nx ny)
 __global__ __launch_bounds__(kThreads) void k_plane_init(ColArgs a) {
   const int nx = a.nx;
@@ -826,6 +943,8 @@ void prepare_dynamic_lds(int max_bytes) {
         (void)hipFuncSetAttribute((const void*)k_col<P, true, false>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col<P, false, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_probe_init<P>, (hipFuncAttribute)attr, max_bytes);
+        if constexpr (res_plan_ok<P>())
+          (void)hipFuncSetAttribute((const void*)k_resident<P>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_colb<P, true, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_colb<P, true, false>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_colb<P, false, true>, (hipFuncAttribute)attr, max_bytes);
@@ -971,6 +1090,48 @@ hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStr
     const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
     hipLaunchKernelGGL((k_probe_init<P>), dim3(grid), dim3(kThreads), lds, st, a);
     e = hipGetLastError();
+  });
+  return e;
+}
+
+// resident slice loop: plan of an N x N grid that fits (0 if none), its threads and LDS bytes
+static int res_plan_for(int n) {
+  // the first plan of n whose lines fill whole wavefronts and whose wave fits one workgroup
+  int found = -1;
+  for (int idx = 0; idx < n_plans(n) && found < 0; ++idx)
+    with_plan(n, idx, [&](auto p) {
+      if constexpr (res_plan_ok<decltype(p)>()) found = idx;
+    });
+  return found;
+}
+
+bool resident_ok(int nx, int ny) { return nx == ny && res_plan_for(nx) >= 0; }
+
+int resident_workgroups_per_cu(int n, int max_lds) {
+  const int idx = res_plan_for(n);
+  int per = 0;
+  if (idx >= 0)
+    with_plan(n, idx, [&](auto p) {
+      using P = decltype(p);
+      if constexpr (res_plan_ok<P>()) {
+        const int by_lds = max_lds / (res_lds_words<P>() * 8);
+        const int by_threads = 2048 / res_threads<P>();
+        per = by_lds < by_threads ? by_lds : by_threads;
+      }
+    });
+  return per > 0 ? per : 1;
+}
+
+hipError_t launch_resident(int n, const ColArgs& a, int grid, hipStream_t st) {
+  const int idx = res_plan_for(n);
+  hipError_t e = hipErrorInvalidValue;
+  if (idx < 0) return e;
+  with_plan(n, idx, [&](auto p) {
+    using P = decltype(p);
+    if constexpr (res_plan_ok<P>()) {
+      hipLaunchKernelGGL((k_resident<P>), dim3(grid), dim3(res_threads<P>()), res_lds_words<P>() * 8, st, a);
+      e = hipGetLastError();
+    }
   });
   return e;
 }
