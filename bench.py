@@ -10,8 +10,15 @@ periodograms accumulated over positions, Kubo correction and normalisation of th
 S(q, omega) of every specimen.
 
 Metric: snapshot-slice steps per second = (probe positions x snapshots x sum of slices) / step time.
+The timed steps replay the captured slice-loop graphs (no instrumentation).  After them: one exit
+wave of the last timed step is recomputed by the FP64 oracle (rel-L2 <= 1e-4, else exit status 3),
+and one instrumented step brackets every kernel with HIP events on its stream for the per-kernel
+durations, algorithmic bandwidths and the roofline of the dominant slice-step pass.
 Side legs (outside the timed region): the plain one-snapshot-per-launch path on a labelled subset
-(batched vs plain), and the adjoint/forward time ratio on the differentiation configuration.
+(batched vs plain), the whole 24-specimen batched-uneven configuration (128^2/256^2/512^2 classes;
+plain, batched and persistent modes), the adjoint/forward time ratio on the differentiation
+configuration, a plane-wave 512^2 batch with the analysis outputs, the 560^2 and 1000^2 grids and
+the large 1024^2 configuration; then the CPU baselines (FP64 oracle, scipy.fft) on the host cores.
 
 Prints ONE JSON line.  Progress goes to stderr.
 """
@@ -44,7 +51,11 @@ def parse():
     p.add_argument("--specimens", type=int, default=8, help="specimens of the 512^2 class (<= 8)")
     p.add_argument("--pos-chunk", type=int, default=8, help="probe positions per batched call")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--no-legs", action="store_true", help="skip the plain and adjoint legs")
+    p.add_argument("--no-legs", action="store_true", help="skip the side legs")
+    p.add_argument("--no-full", action="store_true",
+                   help="skip the whole 24-specimen batched-uneven leg")
+    p.add_argument("--no-check", action="store_true",
+                   help="skip the oracle check of one exit wave of the timed work")
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
     p.add_argument("--calibrate", action="store_true",
                    help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
@@ -59,13 +70,15 @@ def parse():
 
 
 # ------------------------------------------------------------------------------------------------
-def make_specimens(n_spec, T, device):
+def make_specimens(n_spec, T, device, grids=(512,)):
     import torch
     from workloads.configs import c3_specimens, make_workload
-    specs = [c for c in c3_specimens() if c["n"] == (512, 512)][:n_spec]
+    specs = []
+    for n in grids:
+        specs += [c for c in c3_specimens() if c["n"] == (n, n)][:n_spec]
     out = []
     for cfg in specs:
-        w = make_workload(cfg, n_snap=T, generate=False, name=f"c3-512-S{cfg['n_slices']}")
+        w = make_workload(cfg, n_snap=T, generate=False, name=f"c3-{cfg['n'][0]}-S{cfg['n_slices']}")
         from workloads.trajectory import harmonic_trajectory
         w.positions = harmonic_trajectory(w.extra["structure"], T, cfg["dt"], cfg["seed"],
                                           device=device)
@@ -74,8 +87,9 @@ def make_specimens(n_spec, T, device):
     return out
 
 
-def run_step(tw, ctx, ws, Vs, exits, Ps, Ss, pos_chunk, events=None):
+def run_step(tw, ctx, ws, Vs, exits, Ps, Ss, pos_chunk, mode=None):
     """One pass of the whole hot path over the batch."""
+    mode = tw.MODE_BATCHED if mode is None else mode
     spec_objs = [tw.specimen_from(w) for w in ws]
     for w, sp, V in zip(ws, spec_objs, Vs):
         tw.tacaw_build_potentials(ctx, sp, w.positions, w.species_dev, w.ff, V)
@@ -85,7 +99,7 @@ def run_step(tw, ctx, ws, Vs, exits, Ps, Ss, pos_chunk, events=None):
         for w, sp, V, ex in zip(ws, spec_objs, Vs, exits):
             b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[c0:c0 + pos_chunk])
             jobs.append(tw.MsJob(sp, b, V, ex))
-        tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
+        tw.tacaw_multislice(ctx, jobs, mode=mode)
         for w, ex, Pacc in zip(ws, exits, Ps):
             tw.tacaw_periodogram(ctx, ex, w.n_e, w.hop, Pacc, accumulate=c0 > 0)
     for w, Pacc, S in zip(ws, Ps, Ss):
@@ -299,6 +313,99 @@ def odd_grid_leg(tw):
     return out
 
 
+def inrun_oracle_check(ws, exits, pos_chunk):
+    """One exit wave of the benchmark's own timed work against the FP64 oracle: the 80-slice
+    specimen, the last snapshot, the first probe position of the last position chunk (the
+    buffers hold that chunk after the timed steps).  The oracle rebuilds the slice potentials of
+    that snapshot from the same float32 positions and propagates the wave by dense DFTs."""
+    from types import SimpleNamespace
+    from oracle import multislice as o_ms
+    from oracle import potential as o_pot
+    k = max(range(len(ws)), key=lambda i: ws[i].n_slices)
+    w = ws[k]
+    t = w.n_snap - 1
+    p0 = ((w.n_pos - 1) // pos_chunk) * pos_chunk
+    t0 = time.perf_counter()
+    pos = w.positions[t:t + 1].float().cpu().numpy()
+    V, _ = o_pot.potentials(pos, w.species, w.ff, w)
+    beam = SimpleNamespace(probe=True, energy_ev=w.energy_ev, alpha_rad=w.alpha_rad,
+                           defocus_a=w.defocus_a, cs_a=w.cs_a, probe_xy=w.probe_xy[p0:p0 + 1])
+    ref = o_ms.exit_waves(V, w, beam)[0, 0]
+    got = exits[k][t, 0].cpu().numpy().astype(np.complex128)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return dict(wave=f"{w.name}: snapshot {t}, probe position {p0}, {w.n_slices} slices, {w.nx}^2",
+                rel_l2=err, tolerance=1e-4, passed=bool(err <= 1e-4),
+                oracle_s=time.perf_counter() - t0)
+
+
+def full_uneven_leg(tw, T=256, pos_chunk=8):
+    """The whole batched-uneven configuration: 24 rocksalt specimens (8 each on 128^2, 256^2 and
+    512^2 grids, 10..80 slices), the 100 keV 30 mrad probe at 8 x 8 positions, T snapshots.  The
+    multislice of all 24 specimens runs as one call per chunk of probe positions; timed once over
+    all 64 positions in the batched mode (one graph of per-slice launches) and in the persistent
+    mode (classes as concurrent graph branches, the 128^2 class in one resident launch), and in
+    the plain mode on a labelled subset (one specimen per class, 4 positions, 16 snapshots)."""
+    import torch
+    ctx = tw.context(0)
+    ws = make_specimens(8, T, "cuda:0", grids=(128, 256, 512))
+    Vs = [torch.empty((T, w.n_slices, w.ny, w.nx), dtype=torch.float32, device="cuda:0") for w in ws]
+    for w, V in zip(ws, Vs):
+        tw.tacaw_build_potentials(ctx, tw.specimen_from(w), w.positions, w.species_dev, w.ff, V)
+    for w in ws:
+        w.positions = None
+    torch.cuda.synchronize()
+    exits = [torch.empty((T, pos_chunk, w.ny, w.nx), dtype=torch.complex64, device="cuda:0") for w in ws]
+    specs = [tw.specimen_from(w) for w in ws]
+    P = ws[0].n_pos
+
+    def jobs_for(c0, npos=pos_chunk, subset=None, nt=None):
+        out = []
+        for i, (w, sp, V, ex) in enumerate(zip(ws, specs, Vs, exits)):
+            if subset is not None and i not in subset:
+                continue
+            b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[c0:c0 + npos])
+            out.append(tw.MsJob(sp, b, V if nt is None else V[:nt], ex if nt is None else ex[:nt, :npos]))
+        return out
+
+    steps = sum(w.n_slices for w in ws) * P * T
+    res = {}
+    for name, mode in (("batched", tw.MODE_BATCHED), ("persistent", tw.MODE_PERSISTENT)):
+        tw.tacaw_multislice(ctx, jobs_for(0), mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c0 in range(0, P, pos_chunk):
+            tw.tacaw_multislice(ctx, jobs_for(c0), mode=mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = dict(seconds=dt, slice_steps_per_s=steps / dt)
+        log(f"[full] {name}: {dt:.2f} s, {steps / dt / 1e6:.3f} M snapshot-slice steps/s")
+    # plain vs batched vs persistent on the subset (exit buffers sliced to 4 positions x 16 snapshots)
+    sub = [i for i, w in enumerate(ws) if w.n_slices == 40]
+    nt = 16
+    sub_steps = sum(ws[i].n_slices for i in sub) * 4 * nt
+    for name, mode in (("plain", tw.MODE_PLAIN), ("batched", tw.MODE_BATCHED),
+                       ("persistent", tw.MODE_PERSISTENT)):
+        j = jobs_for(0, npos=4, subset=sub, nt=nt)
+        j = [tw.MsJob(x.spec, x.beam, x.V.contiguous(), torch.empty((nt, 4, x.spec.ny, x.spec.nx),
+                      dtype=torch.complex64, device="cuda:0")) for x in j]
+        tw.tacaw_multislice(ctx, j, mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            tw.tacaw_multislice(ctx, j, mode=mode)
+        torch.cuda.synchronize()
+        res[f"subset_{name}_slice_steps_per_s"] = sub_steps * 3 / (time.perf_counter() - t0)
+    res["subset"] = "the 40-slice specimen of each class, 4 probe positions x 16 snapshots"
+    res["persistent_over_batched"] = res["persistent"]["slice_steps_per_s"] / res["batched"]["slice_steps_per_s"]
+    res["subset_batched_over_plain"] = res["subset_batched_slice_steps_per_s"] / res["subset_plain_slice_steps_per_s"]
+    res["workload"] = ("24 rocksalt specimens (8 x 128^2, 8 x 256^2, 8 x 512^2; 10..80 slices), "
+                       f"30 mrad probe at 8x8 positions, {T} snapshots; multislice only")
+    res["slice_steps"] = steps
+    del Vs, exits
+    torch.cuda.empty_cache()
+    return res
+
+
 def large_run(tw, chunk=64, keep=False):
     """The large configuration at full size: B/N-like hexagonal crystal of 40 x 40 x 50 cells
     (640,000 atoms), 1024^2 grid, 100 slices of 3.33 A, 60 keV plane wave, 2048 snapshots at 2 fs
@@ -373,6 +480,24 @@ def structure_factor_work(ws):
 
 
 # ------------------------------------------------------------------------------------------------
+def host_info():
+    """Host cores and CPU model of the machine the baselines run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return dict(nproc=avail, cpu_count=os.cpu_count(), model=model)
+
+
 def cpu_baseline(budget_s):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload: one 512^2
     specimen slab of 10 slices, 2 snapshots x 2 probe positions (40 slice steps, 20 potential
@@ -395,12 +520,55 @@ def cpu_baseline(budget_s):
     n_steps = V.shape[0] * w.probe_xy.shape[0] * w.n_slices
     per_step = t_ms / n_steps + (t_pot / n_maps) / 64.0
     threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
-    return {"value": 1.0 / per_step, "unit": "snapshot-slice steps/s", "cores": threads or os.cpu_count(),
-            "kind": "oracle",
-            "sample": f"512^2 rocksalt slab, 10 slices, 2 snapshots x 2 probe positions: {n_maps} "
-                      f"potential maps in {t_pot:.1f} s, {n_steps} dense-DFT slice steps in "
-                      f"{t_ms:.1f} s; scaled to 1 map per 64 positions",
-            "wall_s": t_pot + t_ms}
+    hi = host_info()
+    out = {"value": 1.0 / per_step, "unit": "snapshot-slice steps/s", "cores": threads or hi["nproc"],
+           "kind": "oracle",
+           "sample": f"512^2 rocksalt slab, 10 slices, 2 snapshots x 2 probe positions: {n_maps} "
+                     f"potential maps in {t_pot:.1f} s, {n_steps} dense-DFT slice steps in "
+                     f"{t_ms:.1f} s; scaled to 1 map per 64 positions",
+           "nproc": hi["nproc"], "cpu_model": hi["model"], "blas_threads": threads,
+           "multislice_only_slice_steps_per_s": n_steps / t_ms,
+           "wall_s": t_pot + t_ms}
+    out["fft_lines"] = cpu_fft_baseline(V, w, ex)
+    return out
+
+
+def cpu_fft_baseline(V, w, ref):
+    """A fairer CPU line than the dense-DFT oracle: the same multislice with scipy.fft (complex128
+    and complex64, workers = the host's cores) on the oracle's slab (same V, probe and
+    propagators), slice steps per second of the multislice alone; checked against the oracle's
+    exit waves."""
+    import scipy.fft as sfft
+    from oracle import multislice as o_ms
+    from oracle.physics import interaction_parameter
+    workers = host_info()["nproc"]
+    psi0 = o_ms.initial_waves(w, w)
+    sigma = interaction_parameter(w.energy_ev)
+    n = w.nx * w.ny
+    out = {"workers": workers, "sample": "the oracle's slab: 10 slices, 2 snapshots x 2 positions, "
+                                         "repeated for at least 2 s"}
+    for name, cdt, rdt in (("complex128", np.complex128, np.float64), ("complex64", np.complex64, np.float32)):
+        props = [o_ms.propagator(w, w.energy_ev, dz).astype(cdt) for dz in w.dz]
+        trans = np.exp(1j * sigma * V).astype(cdt)
+        steps, t0, exits = 0, time.perf_counter(), None
+        while True:
+            exits = np.empty((V.shape[0], psi0.shape[0], w.ny, w.nx), dtype=cdt)
+            for t in range(V.shape[0]):
+                for p in range(psi0.shape[0]):
+                    psi = psi0[p].astype(cdt)
+                    for s in range(V.shape[1]):
+                        k = sfft.fft2(trans[t, s] * psi, workers=workers)
+                        if s < V.shape[1] - 1:
+                            psi = sfft.ifft2(props[s] * k, workers=workers)
+                        else:
+                            exits[t, p] = props[s] * k / np.sqrt(n).astype(rdt)
+                    steps += V.shape[1]
+            if time.perf_counter() - t0 >= 2.0:
+                break
+        dt = time.perf_counter() - t0
+        err = float(np.linalg.norm(exits - ref) / np.linalg.norm(ref))
+        out[name] = {"slice_steps_per_s": steps / dt, "rel_l2_vs_oracle": err}
+    return out
 
 
 def traffic_record():
@@ -502,7 +670,7 @@ def main():
         run_step(tw, ctx, ws, Vs, exits, Ps, Ss, args.pos_chunk)
         torch.cuda.synchronize()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    tw.tacaw_set_timing(ctx, True)
+    # timed steps: the batched multislice calls replay their captured graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -511,10 +679,24 @@ def main():
         log(f"[bench] step {i + 1}/{args.steps} done")
     dt = time.perf_counter() - t0
     torch.cuda.synchronize()
-    kinds = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col", "sf", "pot_ifft", "pgram")}
-    tw.tacaw_set_timing(ctx, False)
     ms_step = dt / args.steps * 1e3
     value = slice_steps * args.steps / dt
+    # correctness of the timed work: one wave of the last timed step against the FP64 oracle
+    check = None
+    if not args.no_check:
+        log("[bench] oracle check of one exit wave of the timed work")
+        check = inrun_oracle_check(ws, exits, args.pos_chunk)
+        log(f"[bench] oracle check: rel-L2 {check['rel_l2']:.2e} ({check['oracle_s']:.1f} s)")
+    # one instrumented step: every kernel bracketed by HIP events on its stream (eager launches of
+    # the same kernels and grids), for the per-kernel durations and bandwidths
+    tw.tacaw_set_timing(ctx, True)
+    torch.cuda.synchronize()
+    ti = time.perf_counter()
+    run_step(tw, ctx, ws, Vs, exits, Ps, Ss, args.pos_chunk)
+    torch.cuda.synchronize()
+    ti = time.perf_counter() - ti
+    kinds = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col", "sf", "pot_ifft", "pgram")}
+    tw.tacaw_set_timing(ctx, False)
     # dominant kernel among the slice-step passes
     dom = max(("row", "col"), key=lambda k: kinds[k]["total_ms"])
     kd = kinds[dom]
@@ -525,26 +707,34 @@ def main():
                 "frac": achieved / PEAK_HBM_GBS,
                 "traffic": (rec or {}).get(f"{dom}_bytes_per_launch_scaled") if rec else None,
                 "algo_bytes_per_launch": kd["algo_bytes"] / max(1, kd["launches"]),
-                "avg_launch_ms": kd["total_ms"] / max(1, kd["launches"])}
-    breakdown = {k: {"launches": v["launches"], "ms": v["total_ms"] / args.steps,
+                "avg_launch_ms": kd["total_ms"] / max(1, kd["launches"]),
+                "timing": "HIP events on the launch stream, one instrumented step after the timed "
+                          "steps (eager launches of the same kernels and grids)"}
+    breakdown = {k: {"launches": v["launches"], "ms": v["total_ms"],
                      "algo_GBps": (v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] else None}
                  for k, v in kinds.items()}
     ms_time = kinds["row"]["total_ms"] + kinds["col"]["total_ms"]
-    extra = {"multislice_only_slice_steps_per_s": slice_steps * args.steps / (ms_time * 1e-3)
-             if ms_time else None,
-             "kernel_ms_per_step": breakdown}
-    cmacs = structure_factor_work(ws) * args.steps
+    extra = {"multislice_only_slice_steps_per_s": slice_steps / (ms_time * 1e-3) if ms_time else None,
+             "kernel_ms_per_step": breakdown,
+             "instrumented_step_ms": ti * 1e3,
+             "graph_replay_step_ms": ms_step,
+             "inrun_oracle_check": check}
+    cmacs = structure_factor_work(ws)
     if kinds["sf"]["total_ms"]:
         extra["structure_factor"] = {
-            "complex_mac_per_step": cmacs / args.steps,
+            "complex_mac_per_step": cmacs,
             "fp32_equivalent_tflops": 8.0 * cmacs / (kinds["sf"]["total_ms"] * 1e-3) / 1e12,
             "note": "8 flops per complex multiply-add over the computed half plane; each is done "
                     "as 3 fp16 matrix-core products of split operands"}
     if not args.no_legs:
         log("[bench] plain vs batched leg")
         extra["plain_vs_batched"] = plain_leg(tw, ctx, ws, Vs)
-        del exits, Ss, Vs, Ps
+        del exits, Ss, Vs, Ps, ws
         torch.cuda.empty_cache()
+        if not args.no_full:
+            log("[bench] the whole batched-uneven configuration (24 specimens, 3 grid classes)")
+            extra["full_uneven_24"] = full_uneven_leg(tw, T=T, pos_chunk=args.pos_chunk)
+            torch.cuda.empty_cache()
         log("[bench] adjoint/forward leg")
         extra["adjoint"] = adjoint_leg(tw)
         torch.cuda.empty_cache()
@@ -560,23 +750,28 @@ def main():
         extra["large_1024"] = large_run(tw)
     cpu = None
     if not args.no_cpu:
-        log("[bench] CPU oracle baseline (host cores)")
+        log("[bench] CPU baselines on the host cores (FP64 oracle, scipy.fft)")
         cpu = cpu_baseline(args.cpu_budget_s)
     line = {
         "metric": "snapshot-slice steps/sec at 512^2 (batched vs plain) + adjoint/forward time ratio",
         "value": value, "unit": "snapshot-slice steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64/f32", "data": "synthetic (seeded harmonic trajectories)",
+        "vs_baseline": None,
+        "dtype": "c64/f32 (structure factor: fp16 x3 split operands on the matrix cores)",
+        "data": "synthetic (seeded harmonic trajectories)",
         "config": {"workload": "batched-uneven 512^2 class: 8 rocksalt specimens 160x160 A, "
                                "10..80 slices, 100 keV 30 mrad probe at 8x8 positions, "
                                f"{T} snapshots at 5 fs, S(q,w) with {min(256, T)} bins",
-                   "grid": 512, "specimens": len(ws), "probe_positions": ws[0].n_pos,
+                   "grid": 512, "specimens": args.specimens, "probe_positions": 64,
                    "snapshots": T, "slice_steps_per_step": slice_steps, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,
     }
     print(json.dumps(line))
+    if check is not None and not check["passed"]:
+        log(f"[bench] oracle check FAILED: rel-L2 {check['rel_l2']:.3e} > 1e-4")
+        sys.exit(3)
 
 
 if __name__ == "__main__":
