@@ -611,7 +611,7 @@ struct Launcher {
   void row(int n, const Sched& sc, bool adj, RowArgs a, long waves, int kxb) {
     if (a.n_groups <= 0) return;
     const int lines = row_lines_per_wave(n, sc.row_plan);
-    const long tasks = (long)a.n_groups * a.ny;
+    const long tasks = (long)a.n_groups * ((a.ny + lines - 1) / lines * lines);
     long g = (tasks + (long)kWaves * lines - 1) / ((long)kWaves * lines);
     g = std::min<long>(g, (long)c->n_cu * 8);
     // bytes per image element: wave in 8, out 8, checkpoint 8, stash 8; per V row 4 (+4 for dL/dV)

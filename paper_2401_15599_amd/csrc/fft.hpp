@@ -329,7 +329,7 @@ TACAW_HD void sincos_phase(float x, float* s, float* c) {
     const double xd = (double)x;
     const double kd = rint(xd * (1.0 / kHalfPi));
     r = (float)fma(-kd, D2, fma(-kd, D1, xd));
-    q = (int)fmod(kd, 4.0) & 3;
+    q = (int)(kd - 4.0 * floor(kd * 0.25));          // kd mod 4 (exact: kd is an integer)
   }
   const float r2 = r * r;
   const float sp = r + r * r2 * fmaf(r2, fmaf(r2, fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f),

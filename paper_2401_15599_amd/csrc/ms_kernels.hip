@@ -122,8 +122,33 @@ __device__ __forceinline__ float2 load_if_nt(const GLOBAL_AS float2* p, bool c) 
   return x;
 }
 
+// Branch-free masked access to one wave image: a raw buffer resource over the image (uniform base,
+// size in bytes) and per-lane byte offsets; a lane whose element is not wanted passes an offset
+// beyond the resource, which the hardware answers with zeros (loads) or drops (stores) without a
+// memory access.  Images are at most 1024 x 1024 complex values (8 MiB), far below the offset used.
+constexpr unsigned kNoElem = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const GLOBAL_AS float2* base, int n_elem) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, n_elem * 8, 0x00020000);
+}
+// aux 2: non-temporal (streamed once).  The offset passes through an empty asm operand so that
+// the optimiser keeps the lane select as a select instead of splitting the access into branches.
+__device__ __forceinline__ unsigned opaque(unsigned x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+v"(x));
+#endif
+  return x;
+}
+template <int AUX> __device__ __forceinline__ float2 bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const f2v x = __builtin_amdgcn_raw_buffer_load_b64(r, opaque(off), 0, AUX);
+  return make_float2(x.x, x.y);
+}
+template <int AUX> __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, float2 v) {
+  const f2v x = {v.x, v.y};
+  __builtin_amdgcn_raw_buffer_store_b64(x, r, opaque(off), 0, AUX);
+}
+
 // column (or row element) index m of an n-point axis inside the job's band
-__device__ __forceinline__ bool in_band(int m, int kxb, int n) { return m <= kxb || m >= n - kxb; }
+__device__ __forceinline__ bool in_band(int m, int kxb, int n) { return (m <= kxb) | (m >= n - kxb); }
 
 // y-pass task -> (wave index, first column): tiles_lo tiles from the start of each wave's columns,
 // then tiles_hi from the end (all tiles when both are 0)
@@ -161,7 +186,9 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
   static_assert(!(ADJ && ONE), "the adjoint x pass evaluates the transmission once per row");
   __shared__ float2 lds_all[kWaves * LINES * P::LDS_LINE];
   __shared__ float2 twl[P::POW2 ? P::NTW * L : 1];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wavefront index is uniform: the tasks, groups and job descriptors below are then read
+  // with scalar loads
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int line = lane / L, l = lane % L;
   float2* lds = lds_all + (wave * LINES + line) * P::LDS_LINE;
   if constexpr (P::POW2) {
@@ -176,31 +203,31 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
   const TwStrided tw{twl + l, L};
   const float2* tab = fft_table_init<P>();
 
-  // rows per image: a power of two (shift and mask) or any other length (division)
-  const int ny = a.ny, ysh = __builtin_ctz(ny);
-  const bool ypow2 = (ny & (ny - 1)) == 0;
-  const int n_tasks = a.n_groups * ny;
+  // rows per image rounded up to whole wavefronts of lines (the LINES lines of a wavefront then
+  // always belong to one image: uniform group index); the rounding rows are skipped
+  const int ny = a.ny, nyp = (ny + LINES - 1) / LINES * LINES, ysh = __builtin_ctz(nyp);
+  const bool ypow2 = (nyp & (nyp - 1)) == 0;
+  const int n_tasks = a.n_groups * nyp;
   const int stride = (int)gridDim.x * kWaves * LINES;
   for (int base = ((int)blockIdx.x * kWaves + wave) * LINES; base < n_tasks; base += stride) {
-    const int task = base + line;
-    if ((!P::FULL && line >= LINES) || task >= n_tasks) continue;
-    const int g = ypow2 ? task >> ysh : task / ny, y = task - g * ny;
+    const int g = ypow2 ? base >> ysh : base / nyp, y = base - g * nyp + line;
+    if ((!P::FULL && line >= LINES) || y >= ny) continue;
     const int2 gr = const_at(a.groups, g);
     CJob& J = job_at(a.jobs, gr.x);
     const int t = gr.y, s = a.s;
     const size_t row = (size_t)y * N;
     const GLOBAL_AS float* vrow = gp(J.V) + ((size_t)(t * J.S + s) * ny) * N + row;
     const float sigma = J.sigma;
-    float vv[ONE ? E : 1];
-    float2 tr[ONE ? 1 : E];
-    if constexpr (ONE) {
+    // the row's V values are loaded together (one wait), then turned into exp(i sigma V)
+    float vv[E];
 #pragma unroll
-      for (int j = 0; j < E; ++j) vv[j] = vrow[l + L * j];
-    } else {
+    for (int j = 0; j < E; ++j) vv[j] = vrow[l + L * j];
+    float2 tr[ONE ? 1 : E];
+    if constexpr (!ONE) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         float sn, cs;
-        sincos_phase(sigma * vrow[l + L * j], &sn, &cs);
+        sincos_phase(sigma * vv[j], &sn, &cs);
         tr[j] = make_float2(cs, sn);
       }
     }
@@ -223,11 +250,12 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
       const int w = t * J.P + p;
       float2 v[E];
       {
-        const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, w, s) + row;
+        const __amdgpu_buffer_rsrc_t in = image_rsrc(pick_buf(J, a.in_buf, w, s), N * ny);
 #pragma unroll
         for (int j = 0; j < E; ++j)
-          v[j] = (PR && (j == E / 2 - 1 || j == E / 2)) ? make_float2(0.f, 0.f)
-                                                         : load_if_nt(in + l + L * j, (rmask >> j) & 1);
+          v[j] = (PR && (j == E / 2 - 1 || j == E / 2))
+                     ? make_float2(0.f, 0.f)
+                     : bload<2>(in, ((rmask >> j) & 1) ? (unsigned)(row + l + L * j) * 8u : kNoElem);
       }
       if (!ADJ && a.store_ckpt) {
         GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, ny) + row;
@@ -264,10 +292,11 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
       }
       if (a.write_out) {
         FFT<P>::template run<false, PR ? 2 : 0>(v, tw, lds, l, tab);
-        GLOBAL_AS float2* out = pick_buf(J, a.out_buf, w, s) + row;
+        const __amdgpu_buffer_rsrc_t out = image_rsrc(pick_buf(J, a.out_buf, w, s), N * ny);
 #pragma unroll
         for (int j = 0; j < E; ++j)
-          if (!(PR && (j == E / 2 - 1 || j == E / 2)) && ((wmask >> j) & 1)) store_nt(out + l + L * j, v[j]);
+          if (!(PR && (j == E / 2 - 1 || j == E / 2)))
+            bstore<2>(out, ((wmask >> j) & 1) ? (unsigned)(row + l + L * j) * 8u : kNoElem, v[j]);
       }
     }
     if constexpr (ADJ) {
@@ -382,11 +411,11 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
     col_task(a, tk, tpw, tpi, wi, col0);
     const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
-    const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s);
+    const __amdgpu_buffer_rsrc_t in = image_rsrc(pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s), nx * N);
     const int m = col0 + c;
     const bool inb = in_band(m, J.kxb, nx);
 #pragma unroll
-    for (int j = 0; j < E; ++j) nxt[j] = load_if(in + (l + L * j) * nx + m, inb);
+    for (int j = 0; j < E; ++j) nxt[j] = bload<0>(in, inb ? (unsigned)((l + L * j) * nx + m) * 8u : kNoElem);
     nxt_px = gp(J.px)[s * nx + m];
     nxt_nm = gp(J.nmax)[m];
   };
@@ -476,12 +505,13 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
     col_task(a, tk, tpw, tpi, wi, col0);
     const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
-    const GLOBAL_AS float2* in = pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s) + col0;
+    const __amdgpu_buffer_rsrc_t in = image_rsrc(pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s), nx * N);
     const int kxb = J.kxb;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int idx = (int)threadIdx.x + k * nthr;
-      nxt[k] = load_if(in + (idx >> csh) * nx + (idx & cmask), in_band(col0 + (idx & cmask), kxb, nx));
+      const int col = col0 + (idx & cmask);
+      nxt[k] = bload<0>(in, in_band(col, kxb, nx) ? (unsigned)((idx >> csh) * nx + col) * 8u : kNoElem);
     }
   };
   int py_job = -1;
@@ -677,12 +707,16 @@ __global__ __launch_bounds__(res_threads<P>()) void k_resident(ColArgs a) {
       // x pass: psi = G_x W, u = exp(i sigma V_s) psi, W' = F_x u
       FFT<P>::template run<true>(v, tw, xl, l);
       {
+        // V of the row: all loads issued together, then the transmission
         const GLOBAL_AS float* vrow = gp(J.V) + ((size_t)(t * S + s) * N + y) * N;
         const float sigma = J.sigma;
+        float vv[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) vv[j] = vrow[l + L * j];
 #pragma unroll
         for (int j = 0; j < E; ++j) {
           float sn, csn;
-          sincos_phase(sigma * vrow[l + L * j], &sn, &csn);
+          sincos_phase(sigma * vv[j], &sn, &csn);
           v[j] = cmul(v[j], make_float2(csn, sn));
         }
       }
