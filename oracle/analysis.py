@@ -1,6 +1,6 @@
 """Analysis outputs of the method's spectra (oracle, FP64; test infrastructure only).
 
-Paper passages followed (Sec. III, Figs. 1 and 2):
+Paper passages followed (the Si and hBN results paragraphs, Figs. 1 and 2):
 * Diffraction patterns from the method: the energy integral of the spectrum at each q, both of the
   classical time-average c~(q, E) (before the detailed-balance correction) and of the corrected
   c(q, E).  Each map is normalised to unit total over the full q grid, so that patterns from

@@ -25,7 +25,7 @@ template <class F> static bool with_plan(int n, int idx, F&& f) {
     case 16: if (idx == 1) f(P16b{}); else f(P16a{}); return true;
     case 32: if (idx == 1) f(P32b{}); else f(P32a{}); return true;
     case 64: if (idx == 1) f(P64b{}); else f(P64a{}); return true;
-    case 128: if (idx == 1) f(P128b{}); else if (idx == 2) f(P128c{}); else f(P128a{}); return true;
+    case 128: if (idx == 1) f(P128b{}); else f(P128a{}); return true;
     case 256: if (idx == 1) f(P256b{}); else if (idx == 2) f(P256c{}); else f(P256a{}); return true;
     case 512: if (idx == 1) f(P512b{}); else f(P512a{}); return true;
     case 1024: if (idx == 1) f(P1024b{}); else f(P1024a{}); return true;
@@ -39,8 +39,8 @@ template <class F> static bool with_plan(int n, int idx, F&& f) {
 
 int n_plans(int n) {
   switch (n) {
-    case 16: case 32: case 64: case 512: case 1024: return 2;
-    case 128: case 256: return 3;
+    case 16: case 32: case 64: case 128: case 512: case 1024: return 2;
+    case 256: return 3;
     case 560: return 4;
     case 1000: return 2;
     default: return 0;
@@ -49,8 +49,7 @@ int n_plans(int n) {
 
 const char* plan_name(int n, int idx) {
   static const char* names[] = {"16:L2:8x2", "16:L4:4x4", "32:L4:8x4", "32:L2:16x2", "64:L8:8x8",
-                                "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "128:L8:8x4x4",
-                                "256:L32:8x8x4",
+                                "64:L4:16x4", "128:L16:8x4x4", "128:L8:16x8", "256:L32:8x8x4",
                                 "256:L16:16x16", "256:L64:4x4x4x4", "512:L64:8x8x8",
                                 "512:L32:16x8x4", "1024:L64:16x16x4", "1024:L64:16x4x16",
                                 "560:L28:4x5x4x7", "560:L56:2x5x2x2x14", "560:L28:20x4x7",
@@ -58,8 +57,8 @@ const char* plan_name(int n, int idx) {
   int base = 0;
   switch (n) {
     case 16: base = 0; break; case 32: base = 2; break; case 64: base = 4; break;
-    case 128: base = 6; break; case 256: base = 9; break; case 512: base = 12; break;
-    case 1024: base = 14; break; case 560: base = 16; break; case 1000: base = 20; break;
+    case 128: base = 6; break; case 256: base = 8; break; case 512: base = 11; break;
+    case 1024: base = 13; break; case 560: base = 15; break; case 1000: base = 19; break;
     default: return "?";
   }
   if (idx < 0 || idx >= n_plans(n)) return "?";
@@ -634,39 +633,76 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_probe_init(ColArgs
 }
 
 // ------------------------------------------------------------------------------------------------
-// Resident slice loop (small square grids).  One workgroup of N lines x L lanes holds a whole wave
-// in registers (E values per lane) and runs every slice of it on the CU: the x transforms in row
-// layout (thread (line, l) holds row y = line, x = l + L j), the y transforms in column layout
-// (column kx = line, y = l + L j), LDS transposes in between.  Per slice step the wave never
-// leaves the CU: HBM sees the V map of the slice, the checkpoints and, once, the exit wave.  The
-// workgroups are persistent: each takes waves wi = blockIdx.x, blockIdx.x + gridDim.x, ... of the
-// class's S-sorted wave list and runs each through its own job's slice count.
+// Resident slice loop (small square grids).  One workgroup of N lines x L lanes keeps a whole wave
+// in LDS for all of its slices, as a table T[y][x] whose rows use the padded exchange layout
+// (element x of row y at y XS + pad(x)).  The x transforms run on the rows and the y transforms
+// on the columns (element y of column c at y XS + pad(c)), each line exchanging in place in its
+// own row or column, so no registers hold the wave between the phases and no transposes are
+// needed; a workgroup barrier separates the phases.  Per slice step HBM sees the V map of the
+// slice and the checkpoints; the wave is read once (entrance, written by the init kernels) and
+// written once (exit).  The workgroups are persistent: each takes waves wi = blockIdx.x,
+// blockIdx.x + gridDim.x, ... of the class's S-sorted wave list and runs each through its own
+// job's slice count.
 template <class P> constexpr int res_line_stride() {
-  // exchange region of one line: padded positions 0 .. pad_of(N - 1), rounded up to an odd count
+  // padded positions 0 .. pad_of(N - 1) of a row, rounded up to an odd count
   return ((P::N - 1 + (P::N - 1) / 8 + 1) | 1);
 }
-template <class P> constexpr int res_lds_words() {
-  constexpr int x = P::N * res_line_stride<P>(), t = P::N * (P::N + 1);
-  return (x > t ? x : t) + P::NTW * P::L;
-}
+template <class P> constexpr int res_lds_words() { return P::N * res_line_stride<P>() + P::NTW * P::L; }
 template <class P> constexpr int max_radix() {
   int m = 0;
   for (int k = 0; k < P::NR; ++k) m = P::radix(k) > m ? P::radix(k) : m;
   return m;
 }
-// one line per thread (N L <= 1024), radix at most 8 (the registers of a 1024-thread workgroup)
+// at most 1024 threads, each taking H = N L / threads lines in turn; at most 8 values per lane and
+// radix 8 (the registers of a 1024-thread workgroup)
+template <class P> constexpr int res_threads() { return P::N * P::L < 1024 ? P::N * P::L : 1024; }
 template <class P> constexpr bool res_plan_ok() {
-  return P::POW2 && P::FULL && P::N <= 128 && P::N * P::L <= 1024 && max_radix<P>() <= 8 &&
-         res_lds_words<P>() * 8 <= 160 * 1024;
+  return P::POW2 && P::FULL && P::N <= 128 && P::E <= 8 && max_radix<P>() <= 8 &&
+         (P::N * P::L) % res_threads<P>() == 0 && res_lds_words<P>() * 8 <= 160 * 1024;
 }
-template <class P> constexpr int res_threads() { return P::N * P::L; }
+
+// A line of the table: position p at base[p * stride] (stride = 1 for rows; pad(c) folded into
+// base and stride XS for column c, whose positions are not padded in the row direction)
+struct TableLine {
+  float2* base;
+  int stride, padded;   // padded: rows (p + p/8); columns: p XS
+  __device__ __forceinline__ float2& operator()(int p) const {
+    return padded ? base[p + (p >> 3)] : base[p * stride];
+  }
+};
+
+// Transform of one line held striped in v, exchanging in place through acc (register stages only:
+// power-of-two plans).  Same stages and index algebra as FFT<P>::run.
+template <int N, int L, bool INV, int NS, int TO, class TW, int R, int... Rest>
+__device__ __forceinline__ void fft_line_rec(float2* v, const TW& tw, const TableLine& acc, int l) {
+  constexpr int E = N / L, B = E / R;
+  stage_compute<N, L, R, NS, INV, TO>(v, tw, (const float2*)nullptr, l);
+  if constexpr (sizeof...(Rest) > 0) {
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc(stage_out_pos<N, L, R, NS>(l, i, r)) = v[i + B * r];
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = acc(l + L * j);
+    fft_line_rec<N, L, INV, NS * R, (NS > 1) ? TO + B * (R - 1) : TO, TW, Rest...>(v, tw, acc, l);
+  }
+}
+template <class P> struct LineFFT;
+template <int N, int L, int... Rs> struct LineFFT<Plan<N, L, Rs...>> {
+  template <bool INV, class TW>
+  __device__ __forceinline__ static void run(float2* v, const TW& tw, const TableLine& acc, int l) {
+    fft_line_rec<N, L, INV, 1, 0, TW, Rs...>(v, tw, acc, l);
+  }
+};
 
 template <class P>
 __global__ __launch_bounds__(res_threads<P>()) void k_resident(ColArgs a) {
-  constexpr int N = P::N, L = P::L, E = P::E, XS = res_line_stride<P>(), TS = N + 1;
-  constexpr int TAB = (N * XS > N * TS ? N * XS : N * TS);
+  constexpr int N = P::N, L = P::L, E = P::E, XS = res_line_stride<P>();
+  constexpr int H = P::N * P::L / res_threads<P>(), NL = N / H;   // lines per thread, per pass
   extern __shared__ float2 lds_mem[];
-  float2* twl = lds_mem + TAB;
+  float2* twl = lds_mem + N * XS;
   const int tid = threadIdx.x, line = tid / L, l = tid % L;
   if (tid < L) {
     float2 t[P::NTW] = {};
@@ -674,42 +710,41 @@ __global__ __launch_bounds__(res_threads<P>()) void k_resident(ColArgs a) {
 #pragma unroll
     for (int k = 0; k < P::NTW; ++k) twl[k * L + tid] = t[k];
   }
-  __syncthreads();
   const TwStrided tw{twl + l, L};
-  float2* xl = lds_mem + line * XS;                // this line's exchange region
   const float inv_n = a.scale;                     // 1 / (N N)
-  const int y = line, c = line;                    // row y (row layout) / column kx (column layout)
   for (int wi = blockIdx.x; wi < a.n_waves; wi += gridDim.x) {
     const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
     const int w = wv.y * J.P + wv.z, S = J.S, t = wv.y;
     GLOBAL_AS float2* img = gp(J.W) + img_off(w, N, N);
-    // the entrance wave W(kx, y), written by the init kernels, in row layout
-    float2 v[E];
+    // the entrance wave W(kx, y), written by the init kernels, into the table (row layout)
+    __syncthreads();                               // the previous wave's last readers are done
+#pragma unroll 1
+    for (int h = 0; h < H; ++h) {
+      const int y = line + h * NL;
+      const TableLine row{lds_mem + y * XS, 1, 1};
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = img[(size_t)y * N + l + L * j];
+      for (int j = 0; j < E; ++j) row(l + L * j) = img[(size_t)y * N + l + L * j];
+    }
+    __syncthreads();
     for (int s = 0; s < S; ++s) {
-      if (s > 0) {
-        // column layout -> row layout through the transpose table [y][kx]
-        __syncthreads();
+      // x pass on rows y: psi = G_x W, u = exp(i sigma V_s) psi, W' = F_x u
+      const bool ck = J.n_ck > 0 && s % J.ck_stride == 0;
+      const float sigma = J.sigma;
+#pragma unroll 1
+      for (int h = 0; h < H; ++h) {
+        const int y = line + h * NL;
+        const TableLine row{lds_mem + y * XS, 1, 1};
+        float2 v[E];
 #pragma unroll
-        for (int j = 0; j < E; ++j) lds_mem[(l + L * j) * TS + c] = v[j];
-        __syncthreads();
+        for (int j = 0; j < E; ++j) v[j] = row(l + L * j);
+        if (ck) {
+          GLOBAL_AS float2* cp = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, N) + (size_t)y * N;
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds_mem[y * TS + l + L * j];
-        __syncthreads();
-      }
-      if (J.n_ck > 0 && s % J.ck_stride == 0) {
-        GLOBAL_AS float2* ck = gp(J.ckpt) + img_off(w * J.n_ck + s / J.ck_stride, N, N) + (size_t)y * N;
-#pragma unroll
-        for (int j = 0; j < E; ++j) ck[l + L * j] = v[j];
-      }
-      // x pass: psi = G_x W, u = exp(i sigma V_s) psi, W' = F_x u
-      FFT<P>::template run<true>(v, tw, xl, l);
-      {
-        // V of the row: all loads issued together, then the transmission
+          for (int j = 0; j < E; ++j) cp[l + L * j] = v[j];
+        }
+        LineFFT<P>::template run<true>(v, tw, row, l);
         const GLOBAL_AS float* vrow = gp(J.V) + ((size_t)(t * S + s) * N + y) * N;
-        const float sigma = J.sigma;
         float vv[E];
 #pragma unroll
         for (int j = 0; j < E; ++j) vv[j] = vrow[l + L * j];
@@ -719,36 +754,45 @@ __global__ __launch_bounds__(res_threads<P>()) void k_resident(ColArgs a) {
           sincos_phase(sigma * vv[j], &sn, &csn);
           v[j] = cmul(v[j], make_float2(csn, sn));
         }
+        LineFFT<P>::template run<false>(v, tw, row, l);
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < E; ++j) row(l + L * j) = v[j];
       }
-      FFT<P>::template run<false>(v, tw, xl, l);
-      // row layout -> column layout
       __syncthreads();
-#pragma unroll
-      for (int j = 0; j < E; ++j) lds_mem[y * TS + l + L * j] = v[j];
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = lds_mem[(l + L * j) * TS + c];
-      __syncthreads();
-      // y pass: F_y, band-limited propagator M P_s, then G_y (or the exit wave after the last slice)
-      FFT<P>::template run<false>(v, tw, xl, l);
+      // y pass on columns c: F_y, band-limited propagator M P_s, then G_y (or the exit wave after
+      // the last slice)
       const bool last = s == S - 1;
-      const int nm = gp(J.nmax)[c];
-      const float2 pxs = cscale(gp(J.px)[(size_t)s * N + c], last ? J.scale_last : inv_n);
       const GLOBAL_AS float2* pys = gp(J.py) + (size_t)s * N;
+#pragma unroll 1
+      for (int h = 0; h < H; ++h) {
+        const int c = line + h * NL;
+        const TableLine col{lds_mem + P::pad(c), XS, 0};
+        float2 v[E];
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int n = l + L * j;
-        const int ns = n < N / 2 ? n : n - N;
-        float2 d = cmul(pxs, pys[n]);
-        if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
-        v[j] = cmul(v[j], d);
-      }
-      if (last) {
+        for (int j = 0; j < E; ++j) v[j] = col(l + L * j);
+        LineFFT<P>::template run<false>(v, tw, col, l);
+        const int nm = gp(J.nmax)[c];
+        const float2 pxs = cscale(gp(J.px)[(size_t)s * N + c], last ? J.scale_last : inv_n);
 #pragma unroll
-        for (int j = 0; j < E; ++j) img[(size_t)(l + L * j) * N + c] = v[j];
-      } else {
-        FFT<P>::template run<true>(v, tw, xl, l);
+        for (int j = 0; j < E; ++j) {
+          const int n = l + L * j;
+          const int ns = n < N / 2 ? n : n - N;
+          float2 d = cmul(pxs, pys[n]);
+          if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
+          v[j] = cmul(v[j], d);
+        }
+        if (last) {
+#pragma unroll
+          for (int j = 0; j < E; ++j) img[(size_t)(l + L * j) * N + c] = v[j];
+        } else {
+          LineFFT<P>::template run<true>(v, tw, col, l);
+          wave_lds_sync();
+#pragma unroll
+          for (int j = 0; j < E; ++j) col(l + L * j) = v[j];
+        }
       }
+      __syncthreads();
     }
   }
 }

@@ -13,7 +13,6 @@ using P64a = Plan<64, 8, 8, 8>;
 using P64b = Plan<64, 4, 16, 4>;
 using P128a = Plan<128, 16, 8, 4, 4>;
 using P128b = Plan<128, 8, 16, 8>;
-using P128c = Plan<128, 8, 8, 4, 4>;   // E = 16 without a radix-16 stage (fewer live registers)
 using P256a = Plan<256, 32, 8, 8, 4>;
 using P256b = Plan<256, 16, 16, 16>;
 using P256c = Plan<256, 64, 4, 4, 4, 4>;
@@ -36,7 +35,6 @@ using P1000b = Plan<1000, 50, 10, 10, 10>;   // E = 20, register stages only
   X("n16 L2 8x2", tacaw::P16a) X("n16 L4 4x4", tacaw::P16b) X("n32 L4 8x4", tacaw::P32a)        \
   X("n32 L2 16x2", tacaw::P32b) X("n64 L8 8x8", tacaw::P64a) X("n64 L4 16x4", tacaw::P64b)       \
   X("n128 L16 8x4x4", tacaw::P128a) X("n128 L8 16x8", tacaw::P128b)                              \
-  X("n128 L8 8x4x4", tacaw::P128c)                                                               \
   X("n256 L32 8x8x4", tacaw::P256a) X("n256 L16 16x16", tacaw::P256b)                            \
   X("n256 L64 4x4x4x4", tacaw::P256c) X("n512 L64 8x8x8", tacaw::P512a)                          \
   X("n512 L32 16x8x4", tacaw::P512b) X("n1024 L64 16x16x4", tacaw::P1024a)                       \

@@ -1,5 +1,5 @@
 """GPU parity on grids whose lengths are not powers of two: 560 (= 2^4 5 7, the grid of the
-paper's Si and hBN runs, Sec. III) and 1000 (= 2^3 5^3, the Fe grid of the magnon example).
+paper's Si and hBN runs, their MD footnotes) and 1000 (= 2^3 5^3, the Fe grid of the magnon example).
 
 Their transforms use plans with odd radices and an in-place LDS last stage; every step of the
 path (potentials, both beams, the uneven batch, the spectrum, the adjoint and the position
