@@ -66,6 +66,9 @@ def parse():
                    help="run only the 560^2 and 1000^2 lines (for kernel traces of their passes)")
     p.add_argument("--large-only", action="store_true",
                    help="run only the large configuration at full size (1024^2, 2048 snapshots)")
+    p.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                   help="turn two rocprofv3 counter files (FETCH_SIZE, WRITE_SIZE) of a --calibrate "
+                        "run into the per-launch HBM traffic record of the 512^2 slice-step passes")
     return p.parse_args()
 
 
@@ -571,6 +574,49 @@ def cpu_fft_baseline(V, w, ref):
     return out
 
 
+def summarize_traffic(fetch_csv, write_csv, out_json):
+    """Per-launch HBM bytes of the 512^2 slice-step passes from FETCH_SIZE and WRITE_SIZE counter
+    runs (KiB per dispatch), each scaled by what the counter reads for the 1 GiB device-to-device
+    copy of the same run (the calibration copy moves 2^30 bytes each way)."""
+    import csv
+
+    def load(path, counter):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        return per
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    copy_f = max(v for (d, k), v in fetch.items() if "copy" in k.lower())
+    copy_w = max(v for (d, k), v in write.items() if "copy" in k.lower())
+    fs, ws = (1 << 30) / (copy_f * 1024.0), (1 << 30) / (copy_w * 1024.0)
+    rec = {"kernel": "slice step passes at 512^2 (batched-uneven workload)",
+           "source_sha256_16": hashlib.sha256(open(os.path.join(
+               ROOT, "paper_2401_15599_amd", "csrc", "ms_kernels.hip"), "rb").read()).hexdigest()[:16],
+           "calibration": {"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                           "FETCH_SIZE_KiB": copy_f, "WRITE_SIZE_KiB": copy_w,
+                           "fetch_scale": fs, "write_scale": ws}}
+    for name, tag in (("row", "k_row<tacaw::Plan<512, 64"), ("col", "k_colb<tacaw::Plan<512, 64")):
+        rd = [v for (d, k), v in fetch.items() if tag in k]
+        wr = [v for (d, k), v in write.items() if tag in k]
+        rec[f"{name}_launches"] = len(rd)
+        rec[f"{name}_read_bytes_per_launch_scaled"] = sum(rd) / max(1, len(rd)) * 1024.0 * fs
+        rec[f"{name}_write_bytes_per_launch_scaled"] = sum(wr) / max(1, len(wr)) * 1024.0 * ws
+        rec[f"{name}_bytes_per_launch_scaled"] = (rec[f"{name}_read_bytes_per_launch_scaled"] +
+                                                  rec[f"{name}_write_bytes_per_launch_scaled"])
+    rec["commands"] = [
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --steps 1 "
+        "--warmup 0 --no-legs --no-cpu --no-check --calibrate",
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --steps 1 "
+        "--warmup 0 --no-legs --no-cpu --no-check --calibrate",
+        "python3 bench.py --summarize-traffic <fetch csv> <write csv> profiles/traffic_slice_step_512.json"]
+    json.dump(rec, open(out_json, "w"), indent=1)
+    return rec
+
+
 def traffic_record():
     """HBM traffic of the dominant kernel from the committed counter summary, if it was taken on
     the current kernel source."""
@@ -624,6 +670,9 @@ def profile_slice_step(args):
 
 def main():
     args = parse()
+    if args.summarize_traffic:
+        print(json.dumps(summarize_traffic(*args.summarize_traffic), indent=1))
+        return
     if args.profile_slice_step:
         profile_slice_step(args)
         return
