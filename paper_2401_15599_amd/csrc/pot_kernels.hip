@@ -475,6 +475,219 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
   }
 }
 
+// Split structure factor over a quarter of k-space (Hermitian mode: band limit on, so the Nyquist
+// row and column are zero).  An atom's x phase at -kx is the conjugate of the one at +kx, so with
+//   P1 = sum yr xr,  P2 = sum yi xi,  P3 = sum yr xi,  P4 = sum yi xr   (kx >= 0, ky >= 0)
+// the sums at (ky, kx) and (ky, -kx) are (P1 - P2) + i (P3 + P4) and (P1 + P2) + i (P4 - P3); the
+// rows ky < 0 follow by conjugation (real V).  Each 32 x 32 block of four real products (twelve
+// split-fp16 MFMAs per 16 atoms, as above) thus yields two output blocks, and phase tables are
+// generated for kx >= 0 only: half the matrix-core work and half the table generation of the
+// half-plane kernel.  One workgroup per (map, 64 x 64 tile of 0 <= kx < nx/2, 0 <= ky < ny/2).
+__global__ __launch_bounds__(256, 3) void k_structure_factor_quarter(SfArgs a) {
+  constexpr int kBytes = 2 * 4 * kTabH * (int)sizeof(_Float16);
+  __shared__ __attribute__((aligned(16))) char tables[kBytes];
+  _Float16* tb = reinterpret_cast<_Float16*>(tables);   // [axis][component][split_at(k, atom / 8)]
+  constexpr int kSfBatch = sf_batch<true>();
+  __shared__ AtomPhase batch[kSfBatch];
+  __shared__ float ffs[kMaxSpecies * 12];
+  const int nx = a.nx, ny = a.ny, hx = nx / 2, hy = ny / 2;
+  const int tx_n = (hx + kTile - 1) / kTile, ty_n = (hy + kTile - 1) / kTile;
+  const int tiles = tx_n * ty_n;
+  const int map = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  if (map >= a.n_maps) return;
+  const int m0 = (tile % tx_n) * kTile, n0 = (tile / tx_n) * kTile;
+  const int TWe = min(kTile, hx - m0), THe = min(kTile, hy - n0);
+  const int t = a.t0 + map / a.s_count, s = map % a.s_count;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < a.n_species * 12; i += 256) ffs[i] = a.ff[i];
+  float2* out = a.vk + (size_t)map * nx * ny;
+  // (n, m) with 0 <= n < ny/2, 0 <= m < nx/2: vp at (n, m), vm at (n, -m), and for n > 0 their
+  // conjugates at (-n, -m) and (-n, m)
+  auto put = [&](int n, int m, float2 vp, float2 vm) {
+    const int mm = m == 0 ? 0 : nx - m;
+    out[(size_t)n * nx + m] = vp;
+    if (m > 0) out[(size_t)n * nx + mm] = vm;
+    if (n > 0) {
+      const size_t rr = (size_t)(ny - n) * nx;
+      out[rr + mm] = make_float2(vp.x, -vp.y);
+      if (m > 0) out[rr + m] = make_float2(vm.x, -vm.y);
+    }
+  };
+  // the Nyquist row and column (zero under the band limit)
+  if (n0 == 0)
+    for (int m = m0 + tid; m < m0 + TWe; m += 256) {
+      out[(size_t)hy * nx + m] = make_float2(0.f, 0.f);
+      if (m > 0) out[(size_t)hy * nx + nx - m] = make_float2(0.f, 0.f);
+    }
+  if (m0 == 0) {
+    for (int n = n0 + tid; n < n0 + THe; n += 256) {
+      out[(size_t)n * nx + hx] = make_float2(0.f, 0.f);
+      if (n > 0) out[(size_t)(ny - n) * nx + hx] = make_float2(0.f, 0.f);
+    }
+    if (n0 == 0 && tid == 0) out[(size_t)hy * nx + hx] = make_float2(0.f, 0.f);
+  }
+  auto zero_tile = [&]() {
+    for (int i = tid; i < TWe * THe; i += 256)
+      put(n0 + i / TWe, m0 + i % TWe, make_float2(0.f, 0.f), make_float2(0.f, 0.f));
+  };
+  // does any k of this tile pass the band limit?  (exact integer table, symmetric in kx)
+  int any = 0;
+  for (int m = m0 + tid; m < m0 + TWe; m += 256) any |= (a.nmax[m] >= n0);
+  if (!__syncthreads_or(any)) {
+    zero_tile();
+    return;
+  }
+  const int lane = tid & 63, w = tid >> 6, wy = w >> 1, wx = w & 1;
+  const int li = lane & 31, lk = lane >> 5;
+  const int* off = a.offsets + (size_t)t * (a.s_count * a.n_species + 1);
+  const AtomPhase* R = (const AtomPhase*)a.arec + (size_t)(t - a.t0) * a.n_atoms;
+  int zfirst = -1, zlast = -1;
+  for (int z = 0; z < a.n_species; ++z)
+    if (off[s * a.n_species + z + 1] > off[s * a.n_species + z]) {
+      if (zfirst < 0) zfirst = z;
+      zlast = z;
+    }
+  if (zlast < 0) {
+    zero_tile();
+    return;
+  }
+  const int tj = 32 * wx + li;
+  // a 32 x 32 block with no kept k skips its matrix-core products (the tables are still generated)
+  const int qn = 32 * wy < THe ? n0 + 32 * wy : (1 << 30);
+  const bool quad_live = __ballot(tj < TWe && a.nmax[m0 + min(tj, TWe - 1)] >= qn) != 0ull;
+  for (int z = 0; z < a.n_species; ++z) {
+    const int j0 = off[s * a.n_species + z], j1 = off[s * a.n_species + z + 1];
+    if (j1 <= j0) continue;
+    v16f p1 = {0}, p2 = {0}, p3 = {0}, p4 = {0};
+    const uint2* Rw = reinterpret_cast<const uint2*>(R);
+    uint2* bw = reinterpret_cast<uint2*>(batch);
+    uint2 nr0 = make_uint2(0u, 0u), nr1 = nr0, nr2 = nr0;
+    if (tid < kSfBatch && j0 + tid < j1) {
+      nr0 = Rw[3 * (j0 + tid)];
+      nr1 = Rw[3 * (j0 + tid) + 1];
+      nr2 = Rw[3 * (j0 + tid) + 2];
+    }
+    for (int c0 = j0; c0 < j1; c0 += kSfChunk) {
+      const int na = min(kSfChunk, j1 - c0);
+      const int bi = (c0 - j0) % kSfBatch;
+      __syncthreads();                        // previous chunk's tables (and batch) are consumed
+      if (bi == 0) {
+        if (tid < kSfBatch) {
+          bw[3 * tid] = nr0;
+          bw[3 * tid + 1] = nr1;
+          bw[3 * tid + 2] = nr2;
+          const int nb = c0 + kSfBatch + tid;
+          if (nb < j1) {
+            nr0 = Rw[3 * nb];
+            nr1 = Rw[3 * nb + 1];
+            nr2 = Rw[3 * nb + 2];
+          }
+        }
+        __syncthreads();
+      }
+      const AtomPhase* arec = batch + bi;
+      {
+        // one item per thread: (axis, block of 8 k, atom pair); every index is below n/2, so the
+        // signed index equals the storage index and a block never wraps
+        const int axis = tid >> 7, k0 = ((tid >> 4) & 7) * 8, pair = tid & 15;
+        const int lim = axis == 0 ? TWe : THe;
+        const int idx = (axis == 0 ? m0 : n0) + k0;
+        float2 f[2], st[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int at = 2 * pair + u;
+          if (at < na && k0 < lim) {
+            const AtomPhase& ap = arec[at];
+            f[u] = phase_factor(idx, axis == 0 ? ap.ux : ap.uy);
+            st[u] = axis == 0 ? ap.sx : ap.sy;
+          } else {
+            f[u] = make_float2(0.f, 0.f);
+            st[u] = make_float2(0.f, 0.f);
+          }
+        }
+        _Float16* row = tb + axis * 4 * kTabH + 2 * (pair & 3);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const h2 rh = __builtin_amdgcn_cvt_pkrtz(f[0].x, f[1].x);
+          const h2 ih = __builtin_amdgcn_cvt_pkrtz(f[0].y, f[1].y);
+          const h2 rl = split_lo(f[0].x, f[1].x, rh);
+          const h2 il = split_lo(f[0].y, f[1].y, ih);
+          _Float16* dst = row + split_at(k0 + q, pair >> 2);
+          *reinterpret_cast<h2*>(dst) = rh;
+          *reinterpret_cast<h2*>(dst + kTabH) = ih;
+          *reinterpret_cast<h2*>(dst + 2 * kTabH) = rl;
+          *reinterpret_cast<h2*>(dst + 3 * kTabH) = il;
+          f[0] = cmul(f[0], st[0]);
+          f[1] = cmul(f[1], st[1]);
+        }
+      }
+      __syncthreads();
+      if (quad_live) {
+        for (int b = 0; 16 * b < na; ++b) {
+          const _Float16* ty = tb + 4 * kTabH + split_at(32 * wy + li, 2 * b + lk);
+          const _Float16* tx = tb + split_at(32 * wx + li, 2 * b + lk);
+          const v8h yrh = *reinterpret_cast<const v8h*>(ty);
+          const v8h yih = *reinterpret_cast<const v8h*>(ty + kTabH);
+          const v8h yrl = *reinterpret_cast<const v8h*>(ty + 2 * kTabH);
+          const v8h yil = *reinterpret_cast<const v8h*>(ty + 3 * kTabH);
+          const v8h xrh = *reinterpret_cast<const v8h*>(tx);
+          const v8h xih = *reinterpret_cast<const v8h*>(tx + kTabH);
+          const v8h xrl = *reinterpret_cast<const v8h*>(tx + 2 * kTabH);
+          const v8h xil = *reinterpret_cast<const v8h*>(tx + 3 * kTabH);
+          // each real product as hi*hi + hi*lo + lo*hi, the four sums interleaved
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xrh, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yih, xih, p2, 0, 0, 0);
+          p3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xih, p3, 0, 0, 0);
+          p4 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yih, xrh, p4, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xrl, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yih, xil, p2, 0, 0, 0);
+          p3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrh, xil, p3, 0, 0, 0);
+          p4 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yih, xrl, p4, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrl, xrh, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yil, xih, p2, 0, 0, 0);
+          p3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yrl, xih, p3, 0, 0, 0);
+          p4 = __builtin_amdgcn_mfma_f32_32x32x16_f16(yil, xrh, p4, 0, 0, 0);
+        }
+      }
+    }
+    // accumulator element r of this lane is (row (r&3) + 4 lk + 8 (r>>2), column li) of the
+    // block; V += f_z(|k|) S_z at (ky, kx) and (ky, -kx), the running sums kept in the output
+    // until the last species, which applies the prefactor and the band limit
+    if (tj < TWe) {
+      const float* f = ffs + 12 * z;
+      int tib = 32 * wy + 4 * lk;
+      asm volatile("" : "+v"(tib));
+      const int m = m0 + tj, mm = m == 0 ? 0 : nx - m;
+      const float kx = (float)m / (float)a.lx;
+      const int nmp = a.nmax[m], nmm = a.nmax[mm];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ti = tib + (r & 3) + 8 * (r >> 2);
+        if (ti >= THe) continue;
+        const int n = n0 + ti;
+        const float ky = (float)n / (float)a.ly;
+        const float fz = form_factor(f, kx * kx + ky * ky);
+        float2 vp = make_float2(0.f, 0.f), vm = vp;
+        if (z != zfirst) {
+          vp = out[(size_t)n * nx + m];
+          vm = out[(size_t)n * nx + mm];
+        }
+        vp.x = fmaf(fz, p1[r] - p2[r], vp.x);
+        vp.y = fmaf(fz, p3[r] + p4[r], vp.y);
+        vm.x = fmaf(fz, p1[r] + p2[r], vm.x);
+        vm.y = fmaf(fz, p4[r] - p3[r], vm.y);
+        if (z == zlast) {
+          put(n, m, n <= nmp ? make_float2(vp.x * a.pref, vp.y * a.pref) : make_float2(0.f, 0.f),
+              n <= nmm ? make_float2(vm.x * a.pref, vm.y * a.pref) : make_float2(0.f, 0.f));
+        } else {
+          out[(size_t)n * nx + m] = vp;
+          if (m > 0) out[(size_t)n * nx + mm] = vm;
+        }
+      }
+    }
+  }
+}
+
 hipError_t launch_atom_phase(const float* xyz, const int* order, int t0, int nt, int n_atoms,
                              double lx, double ly, void* rec, hipStream_t st) {
   const long total = (long)nt * n_atoms;
@@ -496,7 +709,10 @@ hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
   const int ty_n = a.hermitian ? (a.ny / 2 + kTile - 1) / kTile : (a.ny + kTile - 1) / kTile;
   const long blocks = (long)a.n_maps * tx_n * ty_n;
   if (blocks <= 0) return hipSuccess;
-  if (a.split16)
+  if (a.split16 && a.hermitian) {
+    const long qb = (long)a.n_maps * ((a.nx / 2 + kTile - 1) / kTile) * ((a.ny / 2 + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_structure_factor_quarter, dim3((unsigned)qb), dim3(256), 0, st, a);
+  } else if (a.split16)
     hipLaunchKernelGGL(k_structure_factor<true>, dim3((unsigned)blocks), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(k_structure_factor<false>, dim3((unsigned)blocks), dim3(256), 0, st, a);
