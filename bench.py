@@ -66,9 +66,11 @@ def parse():
                    help="run only the 560^2 and 1000^2 lines (for kernel traces of their passes)")
     p.add_argument("--large-only", action="store_true",
                    help="run only the large configuration at full size (1024^2, 2048 snapshots)")
-    p.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+    p.add_argument("--summarize-traffic", nargs=4,
+                   metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_RUN_JSON", "OUT_JSON"),
                    help="turn two rocprofv3 counter files (FETCH_SIZE, WRITE_SIZE) of a --calibrate "
-                        "run into the per-launch HBM traffic record of the 512^2 slice-step passes")
+                        "run (and the JSON line that run printed) into the HBM traffic record of the "
+                        "512^2 slice-step passes")
     return p.parse_args()
 
 
@@ -90,8 +92,11 @@ def make_specimens(n_spec, T, device, grids=(512,)):
     return out
 
 
-def run_step(tw, ctx, ws, Vs, exits, Ps, Ss, pos_chunk, mode=None):
-    """One pass of the whole hot path over the batch."""
+def run_step(tw, ctx, ws, Vs, exits, Ps, Ss, pos_chunk, mode=None, ms_events=None):
+    """One pass of the whole hot path over the batch.  With ms_events (a list), a pair of CUDA
+    events on the caller's stream brackets every multislice call (the library joins its side
+    streams back into that stream before the call returns)."""
+    import torch
     mode = tw.MODE_BATCHED if mode is None else mode
     spec_objs = [tw.specimen_from(w) for w in ws]
     for w, sp, V in zip(ws, spec_objs, Vs):
@@ -102,7 +107,13 @@ def run_step(tw, ctx, ws, Vs, exits, Ps, Ss, pos_chunk, mode=None):
         for w, sp, V, ex in zip(ws, spec_objs, Vs, exits):
             b = tw.Beam(w.energy_ev, True, w.alpha_rad, 0.0, 0.0, w.probe_xy[c0:c0 + pos_chunk])
             jobs.append(tw.MsJob(sp, b, V, ex))
+        if ms_events is not None:
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record()
         tw.tacaw_multislice(ctx, jobs, mode=mode)
+        if ms_events is not None:
+            ev[1].record()
+            ms_events.append(ev)
         for w, ex, Pacc in zip(ws, exits, Ps):
             tw.tacaw_periodogram(ctx, ex, w.n_e, w.hop, Pacc, accumulate=c0 > 0)
     for w, Pacc, S in zip(ws, Ps, Ss):
@@ -297,11 +308,13 @@ def odd_grid_leg(tw):
             tw.tacaw_multislice(ctx, job, mode=tw.MODE_BATCHED)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+        tw.tacaw_set_slice_blocking(ctx, tw.SLICE_BLOCK_BYTES, 1)   # one stream: no overlap
         tw.tacaw_set_timing(ctx, True)
         tw.tacaw_multislice(ctx, job, mode=tw.MODE_BATCHED)
         torch.cuda.synchronize()
         kinds = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col")}
         tw.tacaw_set_timing(ctx, False)
+        tw.tacaw_set_slice_blocking(ctx, tw.SLICE_BLOCK_BYTES, tw.SLICE_BLOCK_STREAMS)
         med = sorted(times)[len(times) // 2]
         steps = T * n_pos * w.n_slices
         out[key] = dict(
@@ -574,10 +587,13 @@ def cpu_fft_baseline(V, w, ref):
     return out
 
 
-def summarize_traffic(fetch_csv, write_csv, out_json):
-    """Per-launch HBM bytes of the 512^2 slice-step passes from FETCH_SIZE and WRITE_SIZE counter
-    runs (KiB per dispatch), each scaled by what the counter reads for the 1 GiB device-to-device
-    copy of the same run (the calibration copy moves 2^30 bytes each way)."""
+def summarize_traffic(fetch_csv, write_csv, bench_json, out_json):
+    """HBM traffic of the 512^2 slice-step passes from FETCH_SIZE and WRITE_SIZE counter runs (KiB
+    per dispatch), each scaled by what the counter reads for the 1 GiB device-to-device copy of the
+    same run (the calibration copy moves 2^30 bytes each way), per launch and as a ratio to the
+    algorithmic bytes per launch that the run's own instrumented step reports (its JSON line).  The
+    counter run has the benchmark's kernels, block size and streams but fewer snapshots: the
+    profiler's counter collection does not survive the ~10^5 dispatches of a full-size run."""
     import csv
 
     def load(path, counter):
@@ -589,6 +605,9 @@ def summarize_traffic(fetch_csv, write_csv, out_json):
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
         return per
 
+    import paper_2401_15599_amd as tw
+    line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    kinds = line["extra"]["kernel_ms_per_step"]
     fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
     copy_f = max(v for (d, k), v in fetch.items() if "copy" in k.lower())
     copy_w = max(v for (d, k), v in write.items() if "copy" in k.lower())
@@ -596,6 +615,8 @@ def summarize_traffic(fetch_csv, write_csv, out_json):
     rec = {"kernel": "slice step passes at 512^2 (batched-uneven workload)",
            "source_sha256_16": hashlib.sha256(open(os.path.join(
                ROOT, "paper_2401_15599_amd", "csrc", "ms_kernels.hip"), "rb").read()).hexdigest()[:16],
+           "slice_block_bytes": tw.SLICE_BLOCK_BYTES,
+           "counter_run": line["config"]["workload"],
            "calibration": {"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
                            "FETCH_SIZE_KiB": copy_f, "WRITE_SIZE_KiB": copy_w,
                            "fetch_scale": fs, "write_scale": ws}}
@@ -607,12 +628,16 @@ def summarize_traffic(fetch_csv, write_csv, out_json):
         rec[f"{name}_write_bytes_per_launch_scaled"] = sum(wr) / max(1, len(wr)) * 1024.0 * ws
         rec[f"{name}_bytes_per_launch_scaled"] = (rec[f"{name}_read_bytes_per_launch_scaled"] +
                                                   rec[f"{name}_write_bytes_per_launch_scaled"])
+        algo = kinds[name]["algo_bytes"] / max(1, kinds[name]["launches"])
+        rec[f"{name}_algo_bytes_per_launch"] = algo
+        rec[f"{name}_traffic_over_algorithmic"] = rec[f"{name}_bytes_per_launch_scaled"] / algo
     rec["commands"] = [
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --steps 1 "
-        "--warmup 0 --no-legs --no-cpu --no-check --calibrate",
+        "--warmup 0 --snapshots 32 --no-legs --no-cpu --no-check --calibrate  (> <fetch json>)",
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --steps 1 "
-        "--warmup 0 --no-legs --no-cpu --no-check --calibrate",
-        "python3 bench.py --summarize-traffic <fetch csv> <write csv> profiles/traffic_slice_step_512.json"]
+        "--warmup 0 --snapshots 32 --no-legs --no-cpu --no-check --calibrate",
+        "python3 bench.py --summarize-traffic <fetch csv> <write csv> <fetch json> "
+        "profiles/traffic_slice_step_512.json"]
     json.dump(rec, open(out_json, "w"), indent=1)
     return rec
 
@@ -627,6 +652,9 @@ def traffic_record():
     src = os.path.join(ROOT, "paper_2401_15599_amd", "csrc", "ms_kernels.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if rec.get("source_sha256_16") != h:
+        return None
+    import paper_2401_15599_amd as tw
+    if rec.get("slice_block_bytes") != tw.SLICE_BLOCK_BYTES:
         return None
     return rec
 
@@ -656,6 +684,7 @@ def profile_slice_step(args):
         jobs.append(tw.MsJob(tw.specimen_from(w), b, V, ex))
     tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
     torch.cuda.synchronize()
+    tw.tacaw_set_slice_blocking(ctx, tw.SLICE_BLOCK_BYTES, 1)   # one stream: no overlap
     tw.tacaw_set_timing(ctx, True)
     tw.tacaw_multislice(ctx, jobs, mode=tw.MODE_BATCHED)
     torch.cuda.synchronize()
@@ -721,12 +750,14 @@ def main():
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     # timed steps: the batched multislice calls replay their captured graphs
     torch.cuda.synchronize()
+    ms_events = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        run_step(tw, ctx, ws, Vs, exits, Ps, Ss, args.pos_chunk)
+        run_step(tw, ctx, ws, Vs, exits, Ps, Ss, args.pos_chunk, ms_events=ms_events)
         torch.cuda.synchronize()
         log(f"[bench] step {i + 1}/{args.steps} done")
     dt = time.perf_counter() - t0
+    ms_graph_s = sum(a.elapsed_time(b) for a, b in ms_events) * 1e-3 / args.steps
     torch.cuda.synchronize()
     ms_step = dt / args.steps * 1e3
     value = slice_steps * args.steps / dt
@@ -737,7 +768,9 @@ def main():
         check = inrun_oracle_check(ws, exits, args.pos_chunk)
         log(f"[bench] oracle check: rel-L2 {check['rel_l2']:.2e} ({check['oracle_s']:.1f} s)")
     # one instrumented step: every kernel bracketed by HIP events on its stream (eager launches of
-    # the same kernels and grids), for the per-kernel durations and bandwidths
+    # the same kernels, grids and snapshot blocks, all on one stream so that no two launches
+    # overlap), for the per-kernel durations and bandwidths
+    tw.tacaw_set_slice_blocking(ctx, tw.SLICE_BLOCK_BYTES, 1)
     tw.tacaw_set_timing(ctx, True)
     torch.cuda.synchronize()
     ti = time.perf_counter()
@@ -746,6 +779,7 @@ def main():
     ti = time.perf_counter() - ti
     kinds = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col", "sf", "pot_ifft", "pgram")}
     tw.tacaw_set_timing(ctx, False)
+    tw.tacaw_set_slice_blocking(ctx, tw.SLICE_BLOCK_BYTES, tw.SLICE_BLOCK_STREAMS)
     # dominant kernel among the slice-step passes
     dom = max(("row", "col"), key=lambda k: kinds[k]["total_ms"])
     kd = kinds[dom]
@@ -754,12 +788,29 @@ def main():
     roofline = {"bound": "hbm", "kernel": f"slice step, {dom} pass (512^2)",
                 "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS,
-                "traffic": (rec or {}).get(f"{dom}_bytes_per_launch_scaled") if rec else None,
+                # counter bytes per launch: this launch's algorithmic bytes times the counter /
+                # algorithmic ratio measured on the same kernels and blocks (smaller batch)
+                "traffic": (rec[f"{dom}_traffic_over_algorithmic"] * kd["algo_bytes"] /
+                            max(1, kd["launches"])) if rec else None,
+                "traffic_note": ("FETCH_SIZE x 2 + WRITE_SIZE counter bytes over algorithmic bytes "
+                                 "of this pass in a 32-snapshot run of the same kernels and blocks "
+                                 "(profiles/traffic_slice_step_512.json), times this run's "
+                                 "algorithmic bytes per launch") if rec else None,
                 "algo_bytes_per_launch": kd["algo_bytes"] / max(1, kd["launches"]),
                 "avg_launch_ms": kd["total_ms"] / max(1, kd["launches"]),
                 "timing": "HIP events on the launch stream, one instrumented step after the timed "
-                          "steps (eager launches of the same kernels and grids)"}
-    breakdown = {k: {"launches": v["launches"], "ms": v["total_ms"],
+                          "steps (eager launches of the same kernels, grids and snapshot blocks "
+                          "on one stream)"}
+    # the whole slice loop as timed: both passes' algorithmic bytes over the multislice calls of
+    # the timed steps (graph replays, blocks overlapping on two streams)
+    loop_bytes = kinds["row"]["algo_bytes"] + kinds["col"]["algo_bytes"]
+    roofline["slice_loop"] = {
+        "achieved": loop_bytes / ms_graph_s / 1e9 if ms_graph_s else None,
+        "frac": loop_bytes / ms_graph_s / 1e9 / PEAK_HBM_GBS if ms_graph_s else None,
+        "seconds_per_step": ms_graph_s, "algo_bytes_per_step": loop_bytes,
+        "timing": "CUDA events on the caller's stream around every multislice call of the timed "
+                  "steps"}
+    breakdown = {k: {"launches": v["launches"], "ms": v["total_ms"], "algo_bytes": v["algo_bytes"],
                      "algo_GBps": (v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] else None}
                  for k, v in kinds.items()}
     ms_time = kinds["row"]["total_ms"] + kinds["col"]["total_ms"]
@@ -773,8 +824,10 @@ def main():
         extra["structure_factor"] = {
             "complex_mac_per_step": cmacs,
             "fp32_equivalent_tflops": 8.0 * cmacs / (kinds["sf"]["total_ms"] * 1e-3) / 1e12,
-            "note": "8 flops per complex multiply-add over the computed half plane; each is done "
-                    "as 3 fp16 matrix-core products of split operands"}
+            "note": "8 flops per complex multiply-add of the contraction over the half plane "
+                    "ky >= 0 (the kernel forms them from four real sums over the quarter kx, ky >= 0 "
+                    "that serve both kx signs, each product as 3 fp16 matrix-core products of "
+                    "split operands)"}
     if not args.no_legs:
         log("[bench] plain vs batched leg")
         extra["plain_vs_batched"] = plain_leg(tw, ctx, ws, Vs)

@@ -170,9 +170,14 @@ typedef struct {
 
 enum {
   TACAW_MODE_PLAIN = 0,    /* one snapshot per launch sequence: 2 launches per slice per snapshot */
-  TACAW_MODE_BATCHED = 1,  /* every wave of a grid class in one launch per slice and pass; the
-                              slice loop is captured into a hipGraph once per call structure
-                              (shapes, slice counts, band, schedule: not buffer addresses) and
+  TACAW_MODE_BATCHED = 1,  /* the waves of a grid class in blocks of consecutive snapshots (by
+                              default about 192 MiB of band-limited wave data each, sized to stay
+                              in the memory-side cache between the passes): each block runs all
+                              of its slices, one launch per slice and pass over the block's waves,
+                              successive blocks alternating between two streams forked from and
+                              joined back into `stream` (tacaw_set_slice_blocking); the slice loop
+                              is captured into a hipGraph once per call structure (shapes, slice
+                              counts, band, schedule, blocking: not buffer addresses) and
                               replayed; at most 32 graphs are kept per context (least recently
                               used first out) */
   TACAW_MODE_PERSISTENT = 2 /* as BATCHED, with the grid classes of a call as concurrent branches of
@@ -375,7 +380,9 @@ const char* tacaw_describe_schedule(tacaw_ctx* ctx, int32_t n);
  * 16 per element and wave.  Batched multislice calls then launch eagerly instead of replaying
  * their hipGraph (the same kernels and grids).
  * tacaw_get_timing waits for the recorded events, sums launches, milliseconds and bytes of one kind
- * (all kinds for NULL or ""), and forgets them. */
+ * (all kinds for NULL or ""), and forgets them.  The library folds recorded pairs into per-kind sums
+ * every 2048 launches (waiting for them), so that a call with many launches keeps few events alive;
+ * timing is meant for eager calls, not for a stream the caller is capturing. */
 typedef struct {
   int64_t launches;
   double total_ms;
@@ -386,6 +393,13 @@ int tacaw_set_timing(tacaw_ctx* ctx, int32_t enable);
  * 1 (default) fp16 hi/lo split on v_mfma_f32_32x32x16_f16, 0 fp32 v_mfma_f32_32x32x2f32.
  * Errors: TACAW_E_ARG (other values). */
 int tacaw_set_potential_precision(tacaw_ctx* ctx, int32_t split16);
+/* Blocking of the batched slice loop on this context (TACAW_MODE_BATCHED, and the classes of
+ * TACAW_MODE_PERSISTENT that are not run by the resident kernel): block_bytes = band-limited wave
+ * bytes (8 ny n_band per wave) per block of consecutive snapshots, 0 = one block per grid class;
+ * streams = 1..3 streams that successive blocks alternate over (1 = the caller's stream only).
+ * Blocking changes the launch order only, never the arithmetic: exit waves are bit-identical for
+ * every setting.  Defaults 192 MiB and 2.  Errors: TACAW_E_ARG. */
+int tacaw_set_slice_blocking(tacaw_ctx* ctx, int64_t block_bytes, int32_t streams);
 int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out);
 
 /* ----------------------------------------------------------------------------------------------

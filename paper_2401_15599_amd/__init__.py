@@ -107,6 +107,7 @@ _SIGS = {
     "tacaw_plan_count": ([_I], ctypes.c_int),
     "tacaw_set_timing": ([_P, _I], ctypes.c_int),
     "tacaw_set_potential_precision": ([_P, _I], ctypes.c_int),
+    "tacaw_set_slice_blocking": ([_P, ctypes.c_int64, _I], ctypes.c_int),
     "tacaw_get_timing": ([_P, ctypes.c_char_p, ctypes.POINTER(KernelStats)], ctypes.c_int),
     "tacaw_set_cache_limits": ([_P, ctypes.c_int64, ctypes.c_int64, _I], ctypes.c_int),
     "tacaw_cache_stats": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -448,6 +449,14 @@ def tacaw_describe_schedule(ctx, n):
 
 def tacaw_set_potential_precision(ctx, split16):
     _check(_lib.tacaw_set_potential_precision(ctx.handle, int(split16)))
+
+
+SLICE_BLOCK_BYTES = 192 << 20     # the library's defaults for tacaw_set_slice_blocking
+SLICE_BLOCK_STREAMS = 2
+
+
+def tacaw_set_slice_blocking(ctx, block_bytes, streams):
+    _check(_lib.tacaw_set_slice_blocking(ctx.handle, int(block_bytes), int(streams)))
 
 
 def tacaw_set_timing(ctx, enable):

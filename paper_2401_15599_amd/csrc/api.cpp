@@ -247,7 +247,11 @@ struct tacaw_ctx {
   };
   bool timing = false;
   int sf_split16 = 1;
-  std::vector<Timed> timed;
+  // batched slice loop: waves per block (bytes of their band-limited columns) and streams
+  int64_t block_bytes = (int64_t)192 << 20;
+  int block_streams = 2;
+  std::vector<Timed> timed;                          // launches whose events are still pending
+  std::map<std::string, tacaw_kernel_stats> timed_sums;   // folded launches per kind
   std::vector<hipEvent_t> ev_pool;
 
   ~tacaw_ctx() {
@@ -312,6 +316,22 @@ hipEvent_t pool_event(tacaw_ctx* c) {
   return e;
 }
 
+// wait for the recorded events, add their launches to the per-kind sums, recycle the events
+void fold_timed(tacaw_ctx* c) {
+  for (auto& t : c->timed) {
+    hip_check(hipEventSynchronize(t.b), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, t.a, t.b), "hipEventElapsedTime");
+    tacaw_kernel_stats& k = c->timed_sums[t.kind];
+    k.launches += 1;
+    k.total_ms += ms;
+    k.algo_bytes += t.bytes;
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timed.clear();
+}
+
 // run `launch`; with timing enabled, bracket it with events on its stream and record the
 // launch's algorithmic bytes under `kind`
 template <class F> void timed_launch(tacaw_ctx* c, hipStream_t st, const char* kind, double bytes,
@@ -325,6 +345,9 @@ template <class F> void timed_launch(tacaw_ctx* c, hipStream_t st, const char* k
   launch();
   hip_check(hipEventRecord(b, st), "hipEventRecord");
   c->timed.push_back({kind, a, b, bytes});
+  // a call can issue tens of thousands of launches: fold the recorded pairs into per-kind sums
+  // every few thousand launches, so that at most that many events are alive
+  if (c->timed.size() >= 2048) fold_timed(c);
 }
 
 void destroy_graph(tacaw_ctx::GraphEntry& g) {
@@ -671,13 +694,13 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
   for (size_t ci = 0; ci < b.classes.size(); ++ci) {
     const ClassPlan& cp = b.classes[ci];
     const hipStream_t st = fork ? c->side[ci % n_side] : st_main;
-    Launcher L{c, st};
     const Sched rs = schedule_for(c, cp.nx);
     const Sched cs = fit_cols(c, cp.ny, schedule_for(c, cp.ny), cp.nx);
     // the staged init kernels use the same column count (their LDS tile is the smaller one)
-    auto do_range = [&](const int2* groups, int ng, const int4* waves, const std::vector<int>& gS,
+    auto do_range = [&](hipStream_t sst, const int2* groups, int ng, const int4* waves, const std::vector<int>& gS,
                         const std::vector<int>& wS, const int4* plane, int nplane,
                         const int4* probe, int nprobe) {
+      Launcher L{c, sst};
       ColArgs ia{};
       ia.jobs = b.jobs_dev;
       ia.out_buf = BUF_W;
@@ -687,13 +710,13 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ia.waves = plane;
         ia.n_waves = nplane;
         long g = std::min<long>(nplane, (long)c->n_cu * 8);
-        hip_check(launch_plane_init(ia, (int)g, st), "plane-wave init");
+        hip_check(launch_plane_init(ia, (int)g, sst), "plane-wave init");
       }
       if (nprobe > 0) {
         ia.waves = probe;
         ia.n_waves = nprobe;
         long g = std::min<long>((long)nprobe * (cp.nx / cs.C), (long)c->n_cu * 8);
-        hip_check(launch_probe_init(cp.ny, cs.col_plan, ia, (int)g, st), "probe init");
+        hip_check(launch_probe_init(cp.ny, cs.col_plan, ia, (int)g, sst), "probe init");
       }
       const int Smax = gS.empty() ? 0 : gS.front();
       for (int s = 0; s < Smax; ++s) {
@@ -790,13 +813,52 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         const bool probe = d.nap != nullptr;
         // the group's waves are contiguous in the class wave list and in the init lists
         const int4* w = waves_dev + wi;
-        do_range(groups_dev + gi, 1, w, gS, wS, probe ? nullptr : w, probe ? 0 : d.P,
+        do_range(st, groups_dev + gi, 1, w, gS, wS, probe ? nullptr : w, probe ? 0 : d.P,
                  probe ? w : nullptr, probe ? d.P : 0);
         wi += d.P;
       }
     } else {
-      do_range(groups_dev, (int)cp.groups.size(), waves_dev, cp.group_S, cp.wave_S, plane_dev,
-               (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size());
+      const double block = (double)c->block_bytes;
+      const double wave_bytes = 8.0 * cp.ny * std::min(cp.nx, 2 * cp.kxb + 1);
+      const int ng = (int)cp.groups.size();
+      if (block <= 0.0 || ng < 2) {
+        do_range(st, groups_dev, ng, waves_dev, cp.group_S, cp.wave_S, plane_dev,
+                 (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size());
+      } else {
+        // entrance waves of the whole class first, then blocks of consecutive snapshots whose
+        // waves fit the memory-side cache run all their slices before the next block starts;
+        // successive blocks alternate between two streams (forked from and joined back into the
+        // caller's), so that one block's launches fill the other's ramp-up and tail
+        do_range(st, groups_dev, 0, waves_dev, {}, {}, plane_dev, (int)cp.plane_waves.size(), probe_dev,
+                 (int)cp.probe_waves.size());
+        const int chains = fork ? 1 : c->block_streams;
+        if (chains > 1) {
+          hip_check(hipEventRecord(c->fork_ev, st), "hipEventRecord");
+          for (int i = 0; i < chains; ++i)
+            hip_check(hipStreamWaitEvent(c->side[i], c->fork_ev, 0), "hipStreamWaitEvent");
+        }
+        int g0 = 0, k = 0;
+        while (g0 < ng) {
+          int g1 = g0;
+          double bytes = 0.0;
+          do {
+            bytes += wave_bytes * b.jobs[cp.groups[g1].x].P;
+            ++g1;
+          } while (g1 < ng && bytes + wave_bytes * b.jobs[cp.groups[g1].x].P <= block);
+          const long w0 = cp.group_wave_prefix[g0], w1 = cp.group_wave_prefix[g1];
+          const std::vector<int> gS(cp.group_S.begin() + g0, cp.group_S.begin() + g1);
+          const std::vector<int> wS(cp.wave_S.begin() + w0, cp.wave_S.begin() + w1);
+          do_range(chains > 1 ? c->side[k % chains] : st, groups_dev + g0, g1 - g0, waves_dev + w0, gS,
+                   wS, nullptr, 0, nullptr, 0);
+          g0 = g1;
+          ++k;
+        }
+        if (chains > 1)
+          for (int i = 0; i < chains; ++i) {
+            hip_check(hipEventRecord(c->join_ev[i], c->side[i]), "hipEventRecord");
+            hip_check(hipStreamWaitEvent(st, c->join_ev[i], 0), "hipStreamWaitEvent");
+          }
+      }
     }
   }
   if (fork) {
@@ -814,7 +876,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
 // every replay.
 std::string graph_key(const MsBuild& b, int ckpt_stride, int mode, tacaw_ctx* c) {
   std::ostringstream k;
-  k << ckpt_stride << '|' << mode;
+  k << ckpt_stride << '|' << mode << '|' << c->block_bytes << '|' << c->block_streams;
   for (const MsJobDev& d : b.jobs)
     k << "|j" << d.T << ',' << d.P << ',' << d.S << ',' << d.nx << ',' << d.ny << ',' << d.kxb << ','
       << d.ck_stride << ',' << d.n_ck << ',' << (d.nap != nullptr);
@@ -989,7 +1051,9 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
     const bool paired = spec->bandlimit > 0.0 && spec->bandlimit < 1.0;
     const double ifft_bytes = 8.0 * fc * fr + (paired ? 8.0 : 16.0) * fc + 4.0;
     const size_t img = (size_t)spec->nx * spec->ny;
-    const size_t budget = (size_t)1 << 30;   // bytes of complex k-space maps per pass
+    // bytes of complex k-space maps per pass: enough maps per launch that the structure factor's
+    // live tiles fill the GPU many times over (a 1024^2 snapshot of 100 slices holds 800 MB)
+    const size_t budget = (size_t)4 << 30;
     int snaps_per = (int)std::max<size_t>(1, budget / (img * 8 * S));
     snaps_per = std::min(snaps_per, (int)n_snap);
     float2* vk = (float2*)workspace(ctx, "vk", (size_t)snaps_per * S * img * sizeof(float2));
@@ -1052,7 +1116,7 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
     float* ffd = upload_vec(ctx, ff_f32(ff, n_species), st, "ff");
     int* nmax = upload_vec(ctx, bandlimit_table(*spec), st, "bl");
     const size_t img = (size_t)spec->nx * spec->ny;
-    const size_t budget = (size_t)1 << 30;
+    const size_t budget = (size_t)4 << 30;
     int snaps_per = (int)std::max<size_t>(1, budget / (img * 8 * S));
     snaps_per = std::min(snaps_per, (int)n_snap);
     float2* gk = (float2*)workspace(ctx, "vk", (size_t)snaps_per * S * img * sizeof(float2));
@@ -1748,28 +1812,33 @@ int tacaw_set_potential_precision(tacaw_ctx* ctx, int32_t split16) {
   });
 }
 
+int tacaw_set_slice_blocking(tacaw_ctx* ctx, int64_t block_bytes, int32_t streams) {
+  return guarded([&] {
+    if (!ctx) fail(TACAW_E_ARG, "null context");
+    if (block_bytes < 0) fail(TACAW_E_ARG, "block_bytes must be >= 0");
+    if (streams < 1 || streams > (int32_t)tacaw_ctx::kSide) fail(TACAW_E_ARG, "streams must be 1..3");
+    ctx->block_bytes = block_bytes;
+    ctx->block_streams = streams;
+  });
+}
+
 int tacaw_get_timing(tacaw_ctx* ctx, const char* kind, tacaw_kernel_stats* out) {
   return guarded([&] {
     use_device(ctx);
     CallScope scope(ctx);
     if (!out) fail(TACAW_E_ARG, "null output");
     *out = tacaw_kernel_stats{0, 0.0, 0.0};
-    std::vector<tacaw_ctx::Timed> keep;
-    for (auto& t : ctx->timed) {
-      if (kind && *kind && t.kind != kind) {
-        keep.push_back(t);
+    fold_timed(ctx);
+    for (auto it = ctx->timed_sums.begin(); it != ctx->timed_sums.end();) {
+      if (kind && *kind && it->first != kind) {
+        ++it;
         continue;
       }
-      hip_check(hipEventSynchronize(t.b), "hipEventSynchronize");
-      float ms = 0.f;
-      hip_check(hipEventElapsedTime(&ms, t.a, t.b), "hipEventElapsedTime");
-      out->launches += 1;
-      out->total_ms += ms;
-      out->algo_bytes += t.bytes;
-      ctx->ev_pool.push_back(t.a);
-      ctx->ev_pool.push_back(t.b);
+      out->launches += it->second.launches;
+      out->total_ms += it->second.total_ms;
+      out->algo_bytes += it->second.algo_bytes;
+      it = ctx->timed_sums.erase(it);
     }
-    ctx->timed.swap(keep);
   });
 }
 
