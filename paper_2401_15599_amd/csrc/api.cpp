@@ -1058,6 +1058,20 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
     snaps_per = std::min(snaps_per, (int)n_snap);
     float2* vk = (float2*)workspace(ctx, "vk", (size_t)snaps_per * S * img * sizeof(float2));
     void* arec = workspace(ctx, "atom_phase", (size_t)snaps_per * n_atoms * 24);
+    // quarter-plane tiles (64 x 64 over 0 <= kx < nx/2, 0 <= ky < ny/2) with a kept k first
+    std::vector<int> order, dead;
+    {
+      const int tx_n = (spec->nx / 2 + 63) / 64, ty_n = (spec->ny / 2 + 63) / 64;
+      for (int ty = 0; ty < ty_n; ++ty)
+        for (int tx = 0; tx < tx_n; ++tx) {
+          bool live = false;
+          for (int m = 64 * tx; m < std::min(64 * tx + 64, spec->nx / 2); ++m) live |= bl[m] >= 64 * ty;
+          (live ? order : dead).push_back(ty * tx_n + tx);
+        }
+    }
+    const int n_live = (int)order.size();
+    order.insert(order.end(), dead.begin(), dead.end());
+    const int* tile_order = upload_vec(ctx, order, st, "sf_tiles");
     for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
       const int nt = std::min(snaps_per, n_snap - t0);
       SfArgs a{};
@@ -1081,6 +1095,8 @@ int tacaw_build_potentials(tacaw_ctx* ctx, const tacaw_specimen* spec, int32_t n
       // V(-k) = conj V(k) holds exactly when the band limit removes the Nyquist row and column
       a.hermitian = (spec->bandlimit > 0.0 && spec->bandlimit < 1.0 && spec->ny >= 128) ? 1 : 0;
       a.split16 = ctx->sf_split16;
+      a.tile_order = tile_order;
+      a.n_live = n_live;
       timed_launch(ctx, st, "sf", 8.0 * img * nt * S, [&] {
         hip_check(launch_structure_factor(a, st), "structure-factor kernel");
       });

@@ -145,6 +145,10 @@ struct SfArgs {
   void* arec;              // workspace: 24-byte phase record per (snapshot of the pass, atom)
   int hermitian;           // compute ky >= 0 only and write the conjugate reflection
   int split16;             // fp16 hi/lo split operands on the f16 matrix cores (else fp32 MFMA)
+  // quarter-plane kernel: tiles of a map in launch order, those with kept k first (n_live of
+  // them), so that consecutive workgroups (dealt round-robin to the XCDs) share the live work
+  const int* tile_order;
+  int n_live;
 };
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st);
 hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, int kxb, int kyb,

@@ -493,7 +493,18 @@ __global__ __launch_bounds__(256, 3) void k_structure_factor_quarter(SfArgs a) {
   const int nx = a.nx, ny = a.ny, hx = nx / 2, hy = ny / 2;
   const int tx_n = (hx + kTile - 1) / kTile, ty_n = (hy + kTile - 1) / kTile;
   const int tiles = tx_n * ty_n;
-  const int map = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  // workgroups 0 .. n_maps n_live - 1 take the tiles with kept k, map by map; the rest the others
+  const int nl = a.n_live, nlive_wg = a.n_maps * nl;
+  const int bid = blockIdx.x;
+  int map, tile;
+  if (bid < nlive_wg) {
+    map = bid / nl;
+    tile = a.tile_order[bid % nl];
+  } else {
+    const int nd = tiles - nl, r = bid - nlive_wg;
+    map = r / nd;
+    tile = a.tile_order[nl + r % nd];
+  }
   if (map >= a.n_maps) return;
   const int m0 = (tile % tx_n) * kTile, n0 = (tile / tx_n) * kTile;
   const int TWe = min(kTile, hx - m0), THe = min(kTile, hy - n0);
