@@ -873,6 +873,18 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_row_plain(PlainArg
   }
 }
 
+// column tiles of width C that hold a column kept by the band kxb (all of them for kxb < 0):
+// tiles [0, lo) and [hs, nx / C)
+__host__ __device__ inline void plain_live_tiles(int nx, int C, int kxb, int& lo, int& hs) {
+  const int tpi = nx / C;
+  lo = tpi;
+  hs = tpi;
+  if (kxb >= 0) {
+    lo = min(tpi, kxb / C + 1);
+    hs = max(lo, (nx - kxb) / C);
+  }
+}
+
 template <class P, bool INV>
 __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col_plain(PlainArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES, CS = P::LDS_LINE;
@@ -884,15 +896,19 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col_plain(PlainArg
   const float2* tab = fft_table_init<P>();
   const int C = a.C, nx = a.nx;
   const int tpi = nx / C;
+  // a tile of columns that are all zero stays zero (and the row pass does not read it): the tasks
+  // cover only the tiles [0, lo) and [hs, tpi) that hold a kept column
+  int lo, hs;
+  plain_live_tiles(nx, C, a.kxb, lo, hs);
+  const int nlt = lo + (tpi - hs);
   // paired: task = (pair p, column tile) transforms A + iB of images 2p, 2p + 1 into image 2p
   const int n_im = a.pair ? (a.n_img + 1) / 2 : a.n_img;
-  const long n_tasks = (long)n_im * tpi;
+  const long n_tasks = (long)n_im * nlt;
   for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
-    const long img = a.pair ? 2 * (task / tpi) : task / tpi;
+    const long img = a.pair ? 2 * (task / nlt) : task / nlt;
     const size_t ioff = (size_t)img * nx * N;
-    const int col0 = (int)(task % tpi) * C;
-    // a tile of columns that are all zero stays zero (and the row pass does not read it)
-    if (a.kxb >= 0 && col0 > a.kxb && col0 + C - 1 < nx - a.kxb) continue;
+    const int k = (int)(task % nlt);
+    const int col0 = (k < lo ? k : hs + (k - lo)) * C;
     const float2* in = (const float2*)a.in + ioff;
     float2* out = (float2*)a.out + ioff;
     const bool second = a.pair && img + 1 < a.n_img;
@@ -1238,7 +1254,9 @@ hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, in
   with_plan(ny, 0, [&](auto p) {
     using P = decltype(p);
     const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
-    long tasks = n_im * (nx / a.C);
+    int lo, hs;
+    plain_live_tiles(nx, a.C, kxb, lo, hs);
+    long tasks = n_im * (lo + (nx / a.C - hs));
     int grid = (int)(tasks < 4096 ? tasks : 4096);
     hipLaunchKernelGGL((k_col_plain<P, true>), dim3(grid), dim3(kThreads), lds, st, a);
     e = hipGetLastError();
