@@ -458,6 +458,19 @@ def large_run(tw, chunk=64, keep=False):
         t_ms += time.perf_counter() - b
         if (t0 // chunk) % 8 == 7:
             log(f"[large] {t0 + n}/{T} snapshots: potentials {t_pot:.1f} s, multislice {t_ms:.1f} s")
+    # per-pass bandwidth: the last chunk's multislice again, launches isolated on one stream and
+    # bracketed by HIP events (algorithmic bytes of the band-limited columns)
+    t0 = ((T - 1) // chunk) * chunk
+    n = T - t0
+    tw.tacaw_set_slice_blocking(ctx, tw.SLICE_BLOCK_BYTES, 1)
+    tw.tacaw_set_timing(ctx, True)
+    tw.tacaw_multislice(ctx, [tw.MsJob(sp, bm, V[:n], ex[t0:t0 + n])], mode=tw.MODE_BATCHED)
+    torch.cuda.synchronize()
+    kinds = {k: tw.tacaw_get_timing(ctx, k) for k in ("row", "col")}
+    tw.tacaw_set_timing(ctx, False)
+    tw.tacaw_set_slice_blocking(ctx, tw.SLICE_BLOCK_BYTES, tw.SLICE_BLOCK_STREAMS)
+    pass_GBps = {k: (v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] else None
+                 for k, v in kinds.items()}
     opts = tw.SpectrumOpts(w.dt_fs, w.temperature_k, w.n_e, w.hop, w.nx, w.ny)
     Pacc = torch.empty((w.n_e, w.ny, w.nx), dtype=torch.float32, device="cuda:0")
     Sq = torch.empty_like(Pacc)
@@ -473,7 +486,7 @@ def large_run(tw, chunk=64, keep=False):
                trajectory_s=t_gen, potentials_s=t_pot, multislice_s=t_ms, spectrum_s=t_sp,
                slice_steps=steps, multislice_slice_steps_per_s=steps / t_ms,
                total_s=t_gen + t_pot + t_ms + t_sp,
-               exit_stack_GB=ex.numel() * 8 / 1e9)
+               exit_stack_GB=ex.numel() * 8 / 1e9, pass_GBps=pass_GBps)
     if keep:
         out["tensors"] = dict(xyz=xyz, V=V, exit=ex, P=Pacc, S=Sq, norm=norm, w=w, ctx=ctx,
                               last_t0=((T - 1) // chunk) * chunk)
@@ -609,8 +622,8 @@ def summarize_traffic(fetch_csv, write_csv, bench_json, out_json):
     line = json.loads(open(bench_json).read().strip().splitlines()[-1])
     kinds = line["extra"]["kernel_ms_per_step"]
     fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
-    copy_f = max(v for (d, k), v in fetch.items() if "copy" in k.lower())
-    copy_w = max(v for (d, k), v in write.items() if "copy" in k.lower())
+    copy_f = max(v for (d, k), v in fetch.items() if "copybuffer" in k.lower())
+    copy_w = max(v for (d, k), v in write.items() if "copybuffer" in k.lower())
     fs, ws = (1 << 30) / (copy_f * 1024.0), (1 << 30) / (copy_w * 1024.0)
     rec = {"kernel": "slice step passes at 512^2 (batched-uneven workload)",
            "source_sha256_16": hashlib.sha256(open(os.path.join(

@@ -503,7 +503,8 @@ struct ClassPlan {
   std::vector<int4> waves;         // (job, t, p, S) same order
   std::vector<int> group_S, wave_S;
   std::vector<long> group_wave_prefix;   // waves in groups [0, g)
-  std::vector<int4> plane_waves, probe_waves;
+  std::vector<int4> plane_waves, probe_waves;   // entrance waves: plane waves; probes at t = 0
+  std::vector<int4> probe_copies;              // probe waves at t > 0: copies of (job, 0, p)
   int Smax = 0;
   int kxb = 0;                     // widest band of the class's jobs (kx index)
   int kyb = 0;                     // largest |ky index| any column of the class's jobs keeps
@@ -617,7 +618,7 @@ MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_st
         int4 w = make_int4(g.x, g.y, p, d.S);
         cp.waves.push_back(w);
         cp.wave_S.push_back(d.S);
-        if (jobs[g.x].beam->kind == TACAW_PROBE) cp.probe_waves.push_back(w);
+        if (jobs[g.x].beam->kind == TACAW_PROBE) (g.y == 0 ? cp.probe_waves : cp.probe_copies).push_back(w);
         else cp.plane_waves.push_back(w);
       }
     }
@@ -699,7 +700,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
     // the staged init kernels use the same column count (their LDS tile is the smaller one)
     auto do_range = [&](hipStream_t sst, const int2* groups, int ng, const int4* waves, const std::vector<int>& gS,
                         const std::vector<int>& wS, const int4* plane, int nplane,
-                        const int4* probe, int nprobe) {
+                        const int4* probe, int nprobe, const int4* copies, int ncopy) {
       Launcher L{c, sst};
       ColArgs ia{};
       ia.jobs = b.jobs_dev;
@@ -717,6 +718,13 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ia.n_waves = nprobe;
         long g = std::min<long>((long)nprobe * (cp.nx / cs.C), (long)c->n_cu * 8);
         hip_check(launch_probe_init(cp.ny, cs.col_plan, ia, (int)g, sst), "probe init");
+      }
+      if (ncopy > 0) {
+        ia.waves = copies;
+        ia.n_waves = ncopy;
+        const long spans = ((long)cp.nx * cp.ny / 2 + 1023) / 1024;
+        long g = std::min<long>((long)ncopy * spans, (long)c->n_cu * 16);
+        hip_check(launch_wave_copy(ia, (int)g, sst), "probe copies");
       }
       const int Smax = gS.empty() ? 0 : gS.front();
       for (int s = 0; s < Smax; ++s) {
@@ -765,6 +773,8 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
     int4* waves_dev = upload_vec(c, cp.waves, st, "waves");
     int4* plane_dev = cp.plane_waves.empty() ? nullptr : upload_vec(c, cp.plane_waves, st, "pw");
     int4* probe_dev = cp.probe_waves.empty() ? nullptr : upload_vec(c, cp.probe_waves, st, "pr");
+    int4* copy_dev = cp.probe_copies.empty() ? nullptr : upload_vec(c, cp.probe_copies, st, "pc");
+    const int ncopy = (int)cp.probe_copies.size();
     if (mode == TACAW_MODE_PERSISTENT && resident_ok(cp.nx, cp.ny)) {
       // entrance waves by the init kernels, then one launch for every wave of the class: each
       // workgroup keeps a wave on its CU through all of that wave's slices and then takes the next
@@ -785,6 +795,13 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
           ia.n_waves = (int)cp.probe_waves.size();
           long g = std::min<long>((long)ia.n_waves * (cp.nx / cs.C), (long)c->n_cu * 8);
           hip_check(launch_probe_init(cp.ny, cs.col_plan, ia, (int)g, st), "probe init");
+        }
+        if (ncopy > 0) {
+          ia.waves = copy_dev;
+          ia.n_waves = ncopy;
+          const long spans = ((long)cp.nx * cp.ny / 2 + 1023) / 1024;
+          long g = std::min<long>((long)ncopy * spans, (long)c->n_cu * 16);
+          hip_check(launch_wave_copy(ia, (int)g, st), "probe copies");
         }
       }
       ColArgs ra{};
@@ -814,7 +831,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         // the group's waves are contiguous in the class wave list and in the init lists
         const int4* w = waves_dev + wi;
         do_range(st, groups_dev + gi, 1, w, gS, wS, probe ? nullptr : w, probe ? 0 : d.P,
-                 probe ? w : nullptr, probe ? d.P : 0);
+                 probe ? w : nullptr, probe ? d.P : 0, nullptr, 0);
         wi += d.P;
       }
     } else {
@@ -823,14 +840,14 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
       const int ng = (int)cp.groups.size();
       if (block <= 0.0 || ng < 2) {
         do_range(st, groups_dev, ng, waves_dev, cp.group_S, cp.wave_S, plane_dev,
-                 (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size());
+                 (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size(), copy_dev, ncopy);
       } else {
         // entrance waves of the whole class first, then blocks of consecutive snapshots whose
         // waves fit the memory-side cache run all their slices before the next block starts;
         // successive blocks alternate between two streams (forked from and joined back into the
         // caller's), so that one block's launches fill the other's ramp-up and tail
         do_range(st, groups_dev, 0, waves_dev, {}, {}, plane_dev, (int)cp.plane_waves.size(), probe_dev,
-                 (int)cp.probe_waves.size());
+                 (int)cp.probe_waves.size(), copy_dev, ncopy);
         const int chains = fork ? 1 : c->block_streams;
         if (chains > 1) {
           hip_check(hipEventRecord(c->fork_ev, st), "hipEventRecord");
@@ -849,7 +866,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
           const std::vector<int> gS(cp.group_S.begin() + g0, cp.group_S.begin() + g1);
           const std::vector<int> wS(cp.wave_S.begin() + w0, cp.wave_S.begin() + w1);
           do_range(chains > 1 ? c->side[k % chains] : st, groups_dev + g0, g1 - g0, waves_dev + w0, gS,
-                   wS, nullptr, 0, nullptr, 0);
+                   wS, nullptr, 0, nullptr, 0, nullptr, 0);
           g0 = g1;
           ++k;
         }
@@ -1209,6 +1226,7 @@ int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, i
         upload_vec(ctx, cp.waves, st, "waves");
         if (!cp.plane_waves.empty()) upload_vec(ctx, cp.plane_waves, st, "pw");
         if (!cp.probe_waves.empty()) upload_vec(ctx, cp.probe_waves, st, "pr");
+        if (!cp.probe_copies.empty()) upload_vec(ctx, cp.probe_copies, st, "pc");
       }
       if (ctx->graphs.size() >= ctx->max_graphs) {
         auto lru = ctx->graphs.begin();

@@ -117,6 +117,8 @@ int col_wave_threads(int n, int plan, int C);
 int plan_lanes(int n, int plan);
 hipError_t launch_probe_init(int n, int plan, const ColArgs& a, int grid, hipStream_t st);
 hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st);
+// waves (job, t, p) := wave (job, 0, p) of the same buffer (entrance waves of probe jobs)
+hipError_t launch_wave_copy(const ColArgs& a, int grid, hipStream_t st);
 // resident slice loop of small square grids (whole wave per workgroup, every slice on the CU):
 // available grids, workgroups per CU, launch over a class's S-sorted wave list (a.scale = 1/(n n))
 bool resident_ok(int nx, int ny);

@@ -811,6 +811,36 @@ __global__ __launch_bounds__(kThreads) void k_plane_init(ColArgs a) {
   }
 }
 
+// Entrance waves of the later snapshots of a probe job: the probe depends on the beam and the
+// position only, so the listed wave (job, t, p) is a copy of the wave (job, 0, p) that the probe
+// kernel wrote.  Tasks are (wave, span of kCopySpan 16-byte units); each thread issues its four
+// loads before its four stores.  All listed waves belong to one grid class (one nx, ny).
+constexpr int kCopySpan = 4 * kThreads;
+__global__ __launch_bounds__(kThreads) void k_wave_copy(ColArgs a) {
+  const int4 w0 = a.waves[0];
+  const long n = (long)job_at(a.jobs, w0.x).nx * job_at(a.jobs, w0.x).ny / 2;   // nx is even
+  const long spans = (n + kCopySpan - 1) / kCopySpan;
+  const long n_tasks = (long)a.n_waves * spans;
+  for (long t = blockIdx.x; t < n_tasks; t += gridDim.x) {
+    // waves copied at the same time share a few sources: each starts at its own span
+    const long wi = t / spans;
+    const int4 wv = a.waves[wi];
+    CJob& J = job_at(a.jobs, wv.x);
+    const GLOBAL_AS float4* src = (const GLOBAL_AS float4*)pick_buf(J, a.out_buf, wv.z, 0);
+    GLOBAL_AS float4* dst = (GLOBAL_AS float4*)pick_buf(J, a.out_buf, wv.y * J.P + wv.z, 0);
+    const long b = ((t % spans + wi * 37) % spans) * kCopySpan + threadIdx.x;
+    if (b + 3 * kThreads < n) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = src[b + u * kThreads];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) dst[b + u * kThreads] = v[u];
+    } else {
+      for (long i = b; i < n; i += kThreads) dst[i] = src[i];
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // plain batched 2-D transforms of contiguous images
 template <class P, bool INV, bool REAL_IN, bool REAL_OUT>
@@ -1232,6 +1262,11 @@ hipError_t launch_resident(int n, const ColArgs& a, int grid, hipStream_t st) {
 
 hipError_t launch_plane_init(const ColArgs& a, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_plane_init, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wave_copy(const ColArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_wave_copy, dim3(grid), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 
