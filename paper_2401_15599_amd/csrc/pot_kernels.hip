@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) void k_structure_factor(SfArgs a) {
 // split-fp16 MFMAs per 16 atoms, as above) thus yields two output blocks, and phase tables are
 // generated for kx >= 0 only: half the matrix-core work and half the table generation of the
 // half-plane kernel.  One workgroup per (map, 64 x 64 tile of 0 <= kx < nx/2, 0 <= ky < ny/2).
-__global__ __launch_bounds__(256, 3) void k_structure_factor_quarter(SfArgs a) {
+__global__ __launch_bounds__(256, 4) void k_structure_factor_quarter(SfArgs a) {
   constexpr int kBytes = 2 * 4 * kTabH * (int)sizeof(_Float16);
   __shared__ __attribute__((aligned(16))) char tables[kBytes];
   _Float16* tb = reinterpret_cast<_Float16*>(tables);   // [axis][component][split_at(k, atom / 8)]
