@@ -1164,6 +1164,26 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
         ctx, pos_grad_table(*spec, ff, n_species, bandlimit_table(*spec), herm, pref, &hbound), st,
         "pg_vtab");
     float* absmax = (float*)workspace(ctx, "pg_absmax", (size_t)snaps_per * S * sizeof(float));
+    // liveness of every (64-wide kx tile, 32-row ky fill) of the visited rows, as the kernel's
+    // tiles and fills are laid out
+    const int* fill_live;
+    {
+      const std::vector<int> blt = bandlimit_table(*spec);
+      const int TW = std::min(64, spec->nx), tx_n = (spec->nx + TW - 1) / TW;
+      const int ny_h = herm ? spec->ny / 2 : spec->ny, nf = (ny_h + 31) / 32;
+      std::vector<int> live((size_t)tx_n * nf, 0);
+      for (int tx = 0; tx < tx_n; ++tx)
+        for (int f = 0; f < nf; ++f) {
+          int minabs = 1 << 30;
+          for (int n = 32 * f; n < std::min(32 * f + 32, ny_h); ++n) {
+            const int ns = n < spec->ny / 2 ? n : n - spec->ny;
+            minabs = std::min(minabs, ns < 0 ? -ns : ns);
+          }
+          for (int m = tx * TW; m < std::min(tx * TW + TW, spec->nx); ++m)
+            if (blt[m] >= minabs) live[(size_t)tx * nf + f] = 1;
+        }
+      fill_live = upload_vec(ctx, live, st, "pg_fills");
+    }
     for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
       const int nt = std::min(snaps_per, n_snap - t0);
       hip_check(launch_fft2_real(spec->nx, spec->ny, grad_V + (size_t)t0 * S * img, gk, nt * S, st),
@@ -1194,6 +1214,7 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
       a.vtab = vtab;
       a.hbound = (float)hbound;
       a.absmax_out = absmax;
+      a.fill_live = fill_live;
       timed_launch(ctx, st, "pos_grad", 0.0, [&] {
         hip_check(launch_position_grad_chunks(a, chunks, cap, count, st), "position-gradient kernel");
       });

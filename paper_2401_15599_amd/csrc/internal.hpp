@@ -169,6 +169,9 @@ struct PgArgs {
   const float* vtab;       // [n_species][ny_h][nx] pref M(k) f_Z(|k|) w(k) (ny_h = ny/2 or ny)
   float hbound;            // max over vtab of |v| max(1, |ky|)
   float* absmax_out;       // [n_maps] workspace: max |Re G|, |Im G| over the visited rows
+  // [kx tile][ky fill of 32 rows]: 1 when some k of it passes the band limit (64-wide kx tiles,
+  // fills of the visited rows), from the exact band table on the host
+  const int* fill_live;
 };
 hipError_t launch_atom_phase(const float* xyz, const int* order, int t0, int nt, int n_atoms,
                              double lx, double ly, void* rec, hipStream_t st);

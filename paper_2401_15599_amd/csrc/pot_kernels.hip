@@ -812,16 +812,12 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
     const int TWe = min(TW, a.nx - m0);   // the last kx tile of a length not a multiple of 64
     v16f cr = {0}, ci = {0}, tr = {0}, ti = {0};
     int used = 0;
+    const int n_fills = (ny_h + kPgKy - 1) / kPgKy;
     for (int n0 = 0; n0 < ny_h; n0 += kPgKy) {
       const int kh = min(kPgKy, ny_h - n0);
-      int minabs_n = 1 << 30;
-      for (int n = n0; n < n0 + kh; ++n) {
-        const int ns = n < a.ny / 2 ? n : n - a.ny;
-        minabs_n = min(minabs_n, ns < 0 ? -ns : ns);
-      }
-      int any = 0;
-      for (int m = m0 + tid; m < m0 + TWe; m += 256) any |= (a.nmax[m] >= minabs_n);
-      if (!__syncthreads_or(any)) continue;     // also: the previous fill's readers are done
+      // fills without a kept k are skipped (the table is uniform across the workgroup)
+      if (!a.fill_live[tx * n_fills + n0 / kPgKy]) continue;
+      __syncthreads();                          // the previous fill's readers are done
       used = 1;
       // H and ky H for (kx = m0 + c, ky rows n0 + 8 kb + q): 8 consecutive ky per thread, each
       // component split as hi = fp16 (round toward zero) and lo = fp16(x - hi) for the pairs of
