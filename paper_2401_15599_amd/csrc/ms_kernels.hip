@@ -146,6 +146,9 @@ template <int AUX> __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t
   __builtin_amdgcn_raw_buffer_store_b64(x, r, opaque(off), 0, AUX);
 }
 
+// wait for every outstanding memory access of this wavefront
+__device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0); }
+
 // column (or row element) index m of an n-point axis inside the job's band
 __device__ __forceinline__ bool in_band(int m, int kxb, int n) { return (m <= kxb) | (m >= n - kxb); }
 
@@ -421,6 +424,10 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
   int py_job = -1;
   int task = blockIdx.x;
   if (task < n_tasks) load(task);
+  // the first tile is waited for here, so that the loop head has no loads of its own pending:
+  // otherwise the wait the compiler places there for them also drains the previous tile's stores
+  // on every later iteration
+  vmem_drain();
   for (; task < n_tasks; task += gridDim.x) {
     float2 v[E];
 #pragma unroll
@@ -516,6 +523,7 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
   int py_job = -1;
   int task = blockIdx.x;
   if (task < n_tasks) load(task);
+  vmem_drain();   // (as in k_colb)
   for (; task < n_tasks; task += gridDim.x) {
     int wi, col0;
     col_task(a, task, tpw, tpi, wi, col0);
