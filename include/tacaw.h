@@ -359,9 +359,11 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
  * per line: {"n": grid, "row": x-pass plan, "col": y-pass plan, "C": columns per tile (power of
  * two <= 64 dividing n), "kind": y-pass kernel (0 staged, 1 workgroup-exchange block, 2
  * wave-per-column; 2 only for plans whose lines fill a wavefront, i.e. not for 560 and 1000),
- * "pp": ping-pong exchange buffers of kind 1 (0/1)}.  C is reduced at launch to what divides the
- * image width and fits the workgroup and the LDS; a wave-per-column request that no width can
- * serve runs the staged kind.  A missing file is not an error.
+ * "pp": ping-pong exchange buffers of kind 1 (0/1; 2: ping-pong and the split-layout transforms,
+ * one workgroup barrier per transform, only for the 512-point plan 8x8x8 with C a multiple of 8)}.
+ * C is reduced at launch to what divides the image width and fits the workgroup and the LDS (a
+ * split request whose reduced C is no longer a multiple of 8 runs pp 1); a wave-per-column
+ * request that no width can serve runs the staged kind.  A missing file is not an error.
  * Errors: TACAW_E_ARG (malformed file). */
 int tacaw_load_tuning(tacaw_ctx* ctx, const char* cache_path);
 /* Number of compiled FFT plans (radix chains and lanes per line) for grid size n, 0 if none. */

@@ -200,7 +200,8 @@ struct Cached {
 struct Sched {
   int row_plan = 0, col_plan = 0, C = 0;
   int col_kind = 1;    // 0 staged tile, 1 block kernel
-  int pp = 1;          // block kernel: ping-pong LDS exchange regions
+  int pp = 1;          // block kernel: ping-pong LDS exchange regions; 2: and the wave-local
+                       // second exchange (plans with one, tiles of whole wavefronts of columns)
 };
 
 }  // namespace
@@ -446,7 +447,7 @@ Sched schedule_for(tacaw_ctx* c, int n) {
   // built-in choices: tacaw_autotune on an MI355X over 1 GiB batches of waves per grid size
   // {n, row plan, column plan, C, kind, pp}
   static const int table[][6] = {{16, 1, 1, 16, 1, 1},  {32, 0, 0, 16, 2, 0},  {64, 0, 0, 64, 1, 0},
-                                 {128, 0, 0, 32, 1, 0}, {256, 0, 1, 32, 2, 0}, {512, 0, 0, 16, 1, 1},
+                                 {128, 0, 0, 32, 1, 0}, {256, 0, 1, 32, 2, 0}, {512, 0, 0, 16, 1, 2},
                                  {1024, 0, 0, 8, 2, 0}, {560, 2, 3, 16, 1, 0},  {1000, 1, 1, 8, 1, 1}};
   Sched s;
   s.row_plan = 0;
@@ -477,6 +478,8 @@ Sched fit_cols(tacaw_ctx* c, int ny, Sched s, int nx) {
     while (s.C > 1 && s.C * L > col_block_max_threads(ny, s.col_plan)) s.C /= 2;
     if (s.pp && col_block_lds_bytes(ny, s.col_plan, s.C, 1) > budget) s.pp = 0;
     while (s.C > 1 && col_block_lds_bytes(ny, s.col_plan, s.C, s.pp) > budget) s.C /= 2;
+    const int cw = col_block_lx_cols(ny, s.col_plan);
+    if (s.pp == 2 && (cw == 0 || s.C % cw != 0)) s.pp = 1;
   } else if (s.col_kind == 2) {
     const int C0 = s.C;
     while (s.C > 1 && (col_wave_threads(ny, s.col_plan, s.C) > 1024 ||
@@ -1923,7 +1926,7 @@ static std::string sched_line(int n, const Sched& s) {
   std::ostringstream o;
   o << "row=" << plan_name(n, s.row_plan) << " col=" << plan_name(n, s.col_plan) << " C=" << s.C
     << (s.col_kind == 1 ? " block" : s.col_kind == 2 ? " wave-per-column" : " staged")
-    << (s.col_kind == 1 && s.pp ? " pingpong" : "");
+    << (s.col_kind == 1 && s.pp ? " pingpong" : "") << (s.col_kind == 1 && s.pp == 2 ? " wave-local-x2" : "");
   return o.str();
 }
 
@@ -1959,7 +1962,9 @@ int tacaw_load_tuning(tacaw_ctx* ctx, const char* path) {
       s.pp = num("pp");
       if (!grid_size_ok(n) || s.row_plan < 0 || s.row_plan >= n_plans(n) || s.col_plan < 0 ||
           s.col_plan >= n_plans(n) || !pow2_in(s.C, 1, 64) || n % s.C != 0 || s.col_kind < 0 ||
-          s.col_kind > 2 || s.pp < 0 || s.pp > 1 || !plan_kind_ok(n, s.col_plan, s.col_kind))
+          s.col_kind > 2 || s.pp < 0 || s.pp > 2 || !plan_kind_ok(n, s.col_plan, s.col_kind) ||
+          (s.pp == 2 && (s.col_kind != 1 || col_block_lx_cols(n, s.col_plan) == 0 ||
+                         s.C % col_block_lx_cols(n, s.col_plan) != 0)))
         fail(TACAW_E_ARG, "malformed tuning entry");
       ctx->sched[n] = s;
     }
@@ -2028,9 +2033,10 @@ int tacaw_autotune(tacaw_ctx* ctx, int32_t n, int32_t n_waves, const char* cache
     }
     for (int cpn = 0; cpn < n_plans(n); ++cpn)
       for (int kind = 0; kind < 3; ++kind)
-      for (int pp = 0; pp < (kind == 1 ? 2 : 1); ++pp)
+      for (int pp = 0; pp < (kind == 1 ? 3 : 1); ++pp)
       for (int C = 4; C <= 64; C *= 2) {
         if (C > n || n % C != 0 || !plan_kind_ok(n, cpn, kind)) continue;
+        if (pp == 2 && (col_block_lx_cols(n, cpn) == 0 || C % col_block_lx_cols(n, cpn) != 0)) continue;
         const int budget = ctx->max_lds - plan_static_lds(n, cpn);
         if (kind == 0 && col_lds_bytes(n, cpn, C) > budget) continue;
         if (kind == 1 && (C * plan_lanes(n, cpn) > col_block_max_threads(n, cpn) ||

@@ -449,6 +449,30 @@ TACAW_HD void stage_compute(float2* v, const TW& tw, const float2* tab = nullptr
   }
 }
 
+// the same stage transposed: butterflies first, then the twiddles (as a matrix, B T becomes T B;
+// the small DFTs are symmetric).  Run in reverse order with inverted exchanges, the stages of a
+// plan compute the same transform (the DFT matrix is symmetric).
+template <int N, int L, int R, int NS, bool INV, int TO = 0, class TW>
+TACAW_HD void stage_compute_T(float2* v, const TW& tw) {
+  constexpr int E = N / L, B = E / R;
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    float2 x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = v[i + B * r];
+    dft<R, INV>(x);
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[TO + i * (R - 1) + r - 1];
+        x[r] = INV ? cmulc(x[r], w) : cmul(x[r], w);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[i + B * r] = x[r];
+  }
+}
+
 // destination of output r of butterfly i of lane l in a radix-R stage with span NS
 template <int N, int L, int R, int NS> TACAW_HD int stage_out_pos(int l, int i, int r) {
   int b = l + L * i;
@@ -517,6 +541,68 @@ template <int E, int... Rest> constexpr bool next_is_lds_stage() {
   else return false;
 }
 template <int... Rest> constexpr int only_radix() { return (Rest + ...); }
+
+// Split-layout transforms of a line spread over a workgroup, for three-stage plans with one
+// butterfly per lane and stage (E = R1 = R2 = R3, L = R1 R2: 512 = 8 x 8 x 8 on 64 lanes).  Write
+// a lane as l = R1 h + d.  In the first exchange lane l reads only positions = d (mod R1); the
+// second exchange writes and reads only such positions, and each is read by a lane with the same
+// d.  So the first stage may run on a lane numbering lo chosen for the loads (any lane of the
+// line), the exchange re-distributes the line to a numbering lx under which one wavefront holds
+// every h of its d, and the second exchange then stays inside that wavefront (no barrier).  The
+// inverse transform runs the same flow backwards (transposed stages, exchanges inverted), so its
+// only workgroup exchange is its last, which hands the line back to the numbering lo for the
+// stores.  Steps are per lane; the caller orders them:
+//   forward:  fwd1(lo) | barrier | fwd2(lx) | wave order | fwd3(lx)
+//   inverse:  inv1(lx) | wave order | inv2(lx) | barrier | inv3(lo)
+// fwd1/fwd2/fwd3/inv1/inv2 use region A of the line, inv2/inv3 region B (inv2 writes B only at
+// positions of its own d).  Twiddles are the plan's (PlanOps::twiddles) for lane lx.
+template <class P> struct SplitFFT {
+  static constexpr int N = P::N, L = P::L, E = P::E;
+  static constexpr int R1 = P::radix(0), R2 = P::radix(1), R3 = P::NR == 3 ? P::radix(2) : 0;
+  static constexpr bool OK = P::POW2 && P::NR == 3 && E == R1 && E == R2 && E == R3 && L == R1 * R2;
+  // lane lo: the first stage (no twiddles) and the first exchange's writes
+  TACAW_HD static void fwd1(float2* v, float2* A, int lo) {
+    stage_compute<N, L, R1, 1, false>(v, (const float2*)nullptr, nullptr, lo);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) A[pad_of<N>(stage_out_pos<N, L, R1, 1>(lo, 0, r))] = v[r];
+  }
+  // lane lx: the first exchange's reads, the second stage, the second exchange's writes (into the
+  // same region: Ain = Aout in the kernels, where all lanes of a wavefront read before any writes)
+  template <class TW>
+  TACAW_HD static void fwd2(float2* v, const TW& tw, const float2* Ain, float2* Aout, int lx) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = Ain[pad_of<N>(lx + L * j)];
+    stage_compute<N, L, R2, R1, false, 0>(v, tw, nullptr, lx);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) Aout[pad_of<N>(stage_out_pos<N, L, R2, R1>(lx, 0, r))] = v[r];
+  }
+  // lane lx: the second exchange's reads and the last stage (output k = lx + L j in v[j])
+  template <class TW> TACAW_HD static void fwd3(float2* v, const TW& tw, const float2* A, int lx) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = A[pad_of<N>(lx + L * j)];
+    stage_compute<N, L, R3, R1 * R2, false, R2 - 1>(v, tw, nullptr, lx);
+  }
+  // inverse (unnormalised), input element k = lx + L j in v[j]
+  template <class TW> TACAW_HD static void inv1(float2* v, const TW& tw, float2* A, int lx) {
+    stage_compute_T<N, L, R3, R1 * R2, true, R2 - 1>(v, tw);
+#pragma unroll
+    for (int j = 0; j < E; ++j) A[pad_of<N>(lx + L * j)] = v[j];
+  }
+  template <class TW>
+  TACAW_HD static void inv2(float2* v, const TW& tw, const float2* A, float2* B, int lx) {
+#pragma unroll
+    for (int r = 0; r < R2; ++r) v[r] = A[pad_of<N>(stage_out_pos<N, L, R2, R1>(lx, 0, r))];
+    stage_compute_T<N, L, R2, R1, true, 0>(v, tw);
+#pragma unroll
+    for (int j = 0; j < E; ++j) B[pad_of<N>(lx + L * j)] = v[j];
+  }
+  // lane lo: output element lo + L j in v[j]
+  TACAW_HD static void inv3(float2* v, const float2* B, int lo) {
+#pragma unroll
+    for (int r = 0; r < R1; ++r) v[r] = B[pad_of<N>(stage_out_pos<N, L, R1, 1>(lo, 0, r))];
+    stage_compute_T<N, L, R1, 1, true>(v, (const float2*)nullptr);
+  }
+};
 
 template <class P> struct PlanOps;
 template <int N, int L, int... Rs> struct PlanOps<Plan<N, L, Rs...>> {

@@ -376,29 +376,46 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col(ColArgs a) {
 // y pass, block variant: a workgroup of C * L threads owns C adjacent columns; thread (c, l) holds
 // rows l + L j of column c (striped for the column transform), loaded and stored with C-wide row
 // segments.  The next tile is prefetched into registers while the current one is transformed.
-// Twiddles live in a small LDS table (lanes sharing l read the same entry); the per-row propagator
-// factors py stay in registers across tiles of the same job.
+// Twiddles stay in registers; the per-row propagator factors py of the current job sit in LDS.
 // (lengths that are not powers of two: at most 512 threads and 2 wavefronts per SIMD, which leaves
 // their longer lines and table twiddles enough registers)
 template <class P> constexpr int colb_max_threads() { return P::POW2 ? 1024 : 512; }
 
-template <class P, bool DOFWD, bool DOINV, bool PR = false>
+// LX: the split-layout transforms (SplitFFT; 512 = 8 x 8 x 8) with one workgroup barrier per
+// transform instead of two.  Loads, the first forward stage, the last inverse stage and the stores
+// keep the numbering (c, l) of the row-segment tiles; the stages in between run on (cx, lx), under
+// which wavefront (d, g) holds the 64 / R2 columns g CW ... and every lane lx = R1 h + d of them.
+template <class P> constexpr bool colb_lx_ok() { return SplitFFT<P>::OK && 64 % P::radix(1) == 0; }
+
+template <class P, bool DOFWD, bool DOINV, bool PR = false, bool LX = false>
 __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_colb(ColArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, CS = P::LDS_LINE, NTW = P::NTW;
+  static_assert(!LX || colb_lx_ok<P>(), "plan without split-layout transforms");
+  using SF = SplitFFT<P>;
   extern __shared__ float2 lds_mem[];
   const int C = a.C, nx = a.nx;
   const int c = (int)threadIdx.x % C, l = (int)threadIdx.x / C;
+  int cx = c, lx = l;
+  if constexpr (LX) {
+    constexpr int R1 = P::radix(0), R2 = P::radix(1), CW = 64 / R2;
+    const int t = (int)threadIdx.x;
+    cx = t % CW + CW * (t / (64 * R1));
+    lx = R1 * ((t / CW) % R2) + (t / 64) % R1;
+  }
+  // numbering of the loads (the forward's first stage, or the inverse's input) and of the stores
+  const int cl = (LX && !DOFWD) ? cx : c, ll = (LX && !DOFWD) ? lx : l;
+  const int cs = (LX && !DOINV) ? cx : c, ls = (LX && !DOINV) ? lx : l;
   float2* reg0 = lds_mem + c * CS;
   float2* reg1 = a.pingpong ? lds_mem + (C + c) * CS : reg0;
+  float2* xreg0 = lds_mem + cx * CS;
+  float2* xreg1 = a.pingpong ? lds_mem + (C + cx) * CS : xreg0;
   float2* twl = lds_mem + (a.pingpong ? 2 : 1) * C * CS;
   float2* pyl = twl + L * NTW;                       // [N] propagator factors of the current job
-  if (c == 0) {
-    float2 t[NTW] = {};
-    PlanOps<P>::twiddles(t, l);
-#pragma unroll
-    for (int k = 0; k < NTW; ++k) twl[l * NTW + k] = t[k];
-  }
-  const float2* tw = twl + l * NTW;
+  // the lane's twiddles stay in registers for the whole kernel (each transform would otherwise
+  // read them from LDS, which the exchanges already keep busy)
+  float2 tw[NTW] = {};
+  PlanOps<P>::twiddles(tw, lx);
+  (void)twl;
   const float2* tab = fft_table_init<P>();   // (lengths that are not powers of two)
   int buf = 0;
   const int s = a.s;
@@ -414,12 +431,12 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
     const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
     const __amdgpu_buffer_rsrc_t in = image_rsrc(pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s), nx * N);
-    const int m = col0 + c;
+    const int m = col0 + cl;
     const bool inb = in_band(m, J.kxb, nx);
 #pragma unroll
-    for (int j = 0; j < E; ++j) nxt[j] = bload<0>(in, inb ? (unsigned)((l + L * j) * nx + m) * 8u : kNoElem);
-    nxt_px = gp(J.px)[s * nx + m];
-    nxt_nm = gp(J.nmax)[m];
+    for (int j = 0; j < E; ++j) nxt[j] = bload<0>(in, inb ? (unsigned)((ll + L * j) * nx + m) * 8u : kNoElem);
+    nxt_px = gp(J.px)[s * nx + col0 + cx];
+    nxt_nm = gp(J.nmax)[col0 + cx];
   };
   int py_job = -1;
   int task = blockIdx.x;
@@ -437,7 +454,9 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
     int wi, col0;
     col_task(a, task, tpw, tpi, wi, col0);
     const int4 wv = const_at(a.waves, wi);
-    const int m = col0 + c;
+    // one-way split tiles: the previous tile's readers of the regions are done (with both ways,
+    // the other transform's barrier already separates them)
+    if constexpr (LX && !(DOFWD && DOINV)) __syncthreads();
     if (wv.x != py_job) {                            // uniform branch
       __syncthreads();                               // previous tile's readers are done
       const GLOBAL_AS float2* pys = gp(job_at(a.jobs, wv.x).py) + s * N;
@@ -450,7 +469,18 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
       py_job = wv.x;
     }
     if (task + (int)gridDim.x < n_tasks) load(task + gridDim.x);
-    if constexpr (DOFWD) FFT<P>::template run_block<false, PR ? 2 : 0>(v, tw, reg0, reg1, l, buf, tab);
+    if constexpr (DOFWD) {
+      if constexpr (LX) {
+        SF::fwd1(v, reg0, l);
+        __syncthreads();
+        SF::fwd2(v, tw, xreg0, xreg0, lx);
+        wave_lds_sync();
+        SF::fwd3(v, tw, xreg0, lx);
+        prune_mid<E, PR ? 2 : 0>(v, 2);
+      } else {
+        FFT<P>::template run_block<false, PR ? 2 : 0>(v, tw, reg0, reg1, l, buf, tab);
+      }
+    }
     if constexpr (PR) prune_mid<E, 1>(v, 1);   // M is zero there (also for a raw adjoint input)
     {
       // band-limited propagator (conjugated for the adjoint; pyl is stored conjugated then)
@@ -458,18 +488,29 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
       if (a.conj_prop) pxs.y = -pxs.y;
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        const int n = l + L * j;
+        const int n = lx + L * j;
         const int ns = n < N / 2 ? n : n - N;
         float2 d = cmul(pxs, pyl[n]);
         if ((ns < 0 ? -ns : ns) > nm) d = make_float2(0.f, 0.f);
         v[j] = cmul(v[j], d);
       }
     }
-    if constexpr (DOINV) FFT<P>::template run_block<true, PR ? 1 : 0>(v, tw, reg0, reg1, l, buf, tab);
+    if constexpr (DOINV) {
+      if constexpr (LX) {
+        wave_lds_sync();
+        SF::inv1(v, tw, xreg0, lx);
+        wave_lds_sync();
+        SF::inv2(v, tw, xreg0, xreg1, lx);
+        __syncthreads();
+        SF::inv3(v, reg1, l);
+      } else {
+        FFT<P>::template run_block<true, PR ? 1 : 0>(v, tw, reg0, reg1, l, buf, tab);
+      }
+    }
     CJob& J = job_at(a.jobs, wv.x);
     GLOBAL_AS float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s);
 #pragma unroll
-    for (int j = 0; j < E; ++j) out[(l + L * j) * nx + m] = v[j];
+    for (int j = 0; j < E; ++j) out[(ls + L * j) * nx + col0 + cs] = v[j];
   }
 }
 
@@ -1053,6 +1094,16 @@ int plan_static_lds(int n, int plan) {
   return b;
 }
 
+// whether a plan's block y pass has the wave-local second exchange, and its columns per wavefront
+int col_block_lx_cols(int n, int plan) {
+  int cw = 0;
+  with_plan(n, plan, [&](auto p) {
+    using P = decltype(p);
+    if constexpr (colb_lx_ok<P>()) cw = 64 / P::radix(1);
+  });
+  return cw;
+}
+
 // which y-pass kinds a plan supports: 0 and 1 always; 2 (wave per column) whole lines per
 // wavefront
 bool plan_kind_ok(int n, int plan, int kind) {
@@ -1092,6 +1143,14 @@ void prepare_dynamic_lds(int max_bytes) {
           (void)hipFuncSetAttribute((const void*)k_colw<P, true, true, true>, (hipFuncAttribute)attr, max_bytes);
           (void)hipFuncSetAttribute((const void*)k_colw<P, true, false, true>, (hipFuncAttribute)attr, max_bytes);
           (void)hipFuncSetAttribute((const void*)k_colw<P, false, true, true>, (hipFuncAttribute)attr, max_bytes);
+        }
+        if constexpr (colb_lx_ok<P>()) {
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, true, false, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, false, false, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, false, true, false, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, true, true, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, true, false, true, true>, (hipFuncAttribute)attr, max_bytes);
+          (void)hipFuncSetAttribute((const void*)k_colb<P, false, true, true, true>, (hipFuncAttribute)attr, max_bytes);
         }
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, true>, (hipFuncAttribute)attr, max_bytes);
         (void)hipFuncSetAttribute((const void*)k_col_plain<P, false>, (hipFuncAttribute)attr, max_bytes);
@@ -1180,14 +1239,25 @@ hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const C
       const int lds = ((a.pingpong ? 2 : 1) * a.C * P::LDS_LINE + P::L * P::NTW + P::N) *
                       (int)sizeof(float2);
       const int threads = a.C * P::L;
-      auto go = [&](auto pr) {
-        constexpr bool PR = decltype(pr)::value;
+      auto go2 = [&](auto pr, auto lx) {
+        constexpr bool PR = decltype(pr)::value, LX = decltype(lx)::value;
         if (dofwd && doinv)
-          hipLaunchKernelGGL((k_colb<P, true, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+          hipLaunchKernelGGL((k_colb<P, true, true, PR, LX>), dim3(grid), dim3(threads), lds, st, a);
         else if (dofwd)
-          hipLaunchKernelGGL((k_colb<P, true, false, PR>), dim3(grid), dim3(threads), lds, st, a);
+          hipLaunchKernelGGL((k_colb<P, true, false, PR, LX>), dim3(grid), dim3(threads), lds, st, a);
         else
-          hipLaunchKernelGGL((k_colb<P, false, true, PR>), dim3(grid), dim3(threads), lds, st, a);
+          hipLaunchKernelGGL((k_colb<P, false, true, PR, LX>), dim3(grid), dim3(threads), lds, st, a);
+      };
+      // pingpong == 2: the wave-local second exchange where the tile is whole wavefronts of its
+      // columns (the same results either way)
+      auto go = [&](auto pr) {
+        if constexpr (colb_lx_ok<P>()) {
+          if (a.pingpong == 2 && a.C % (64 / P::radix(1)) == 0) {
+            go2(pr, std::true_type{});
+            return;
+          }
+        }
+        go2(pr, std::false_type{});
       };
       bool done = false;
       if constexpr (P::E >= 8 && P::POW2) {
