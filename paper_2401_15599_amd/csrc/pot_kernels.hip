@@ -803,6 +803,7 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
     }
   }
   const float inv_hs = 1.f / hs;
+  const float inv_ly = (float)(1.0 / (double)a.ly);
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) { sx[r] = 0.f; sy[r] = 0.f; }
@@ -825,19 +826,26 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
       {
         const int c = tid & 63, kb = tid >> 6;
         const int m = m0 + c;
+        // the eight rows' G and factor-table values are loaded together (one wait); a position
+        // outside the tile reads element 0 and is then taken as zero
+        float vq[8];
+        float2 gq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int n = n0 + 8 * kb + q;
+          const size_t idx = (c < TWe && n < n0 + kh) ? (size_t)n * a.nx + m : 0;
+          vq[q] = vt[idx];
+          gq[q] = G[idx];
+        }
         float comps[4][8];   // Re H, Im H, Re ky H, Im ky H
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int n = n0 + 8 * kb + q;
-          float2 h = make_float2(0.f, 0.f);
-          float ky = 0.f;
-          if (c < TWe && n < n0 + kh) {
-            const int ns = n < a.ny / 2 ? n : n - a.ny;
-            ky = (float)ns / (float)a.ly;
-            const float v = vt[(size_t)n * a.nx + m] * hs;
-            const float2 g = G[(size_t)n * a.nx + m];
-            h = make_float2(g.x * v, -g.y * v);
-          }
+          const bool in = c < TWe && n < n0 + kh;
+          const int ns = n < a.ny / 2 ? n : n - a.ny;
+          const float ky = in ? (float)ns * inv_ly : 0.f;
+          const float v = in ? vq[q] * hs : 0.f;
+          const float2 h = make_float2(gq[q].x * v, -gq[q].y * v);
           comps[0][q] = h.x;
           comps[1][q] = h.y;
           comps[2][q] = ky * h.x;
