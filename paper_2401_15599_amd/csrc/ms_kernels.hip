@@ -164,6 +164,22 @@ __device__ __forceinline__ void col_task(const ColArgs& a, int task, int tpw, in
   col0 = (jt < a.tiles_lo || a.tiles_hi == 0 ? jt : jt + tpi - a.tiles_lo - a.tiles_hi) * a.C;
 }
 
+// The y pass's propagator rows py of the job of `task` (conjugated for the adjoint) into LDS;
+// returns that job.  The caller separates the writes from their readers with a barrier.
+template <int N>
+__device__ __forceinline__ int load_py_rows(const ColArgs& a, int task, int tpw, int tpi, float2* pyl) {
+  int wi, col0;
+  col_task(a, task, tpw, tpi, wi, col0);
+  const int job = const_at(a.waves, wi).x;
+  const GLOBAL_AS float2* pys = gp(job_at(a.jobs, job).py) + a.s * N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    float2 q = pys[i];
+    if (a.conj_prop) q.y = -q.y;
+    pyl[i] = q;
+  }
+  return job;
+}
+
 // Lengths that are not powers of two ask the compiler for at least 3 wavefronts per SIMD (2 for
 // the adjoint x pass, which holds three line-sized arrays); their transforms would otherwise take
 // every register for instruction-level parallelism.
@@ -440,11 +456,15 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
   };
   int py_job = -1;
   int task = blockIdx.x;
-  if (task < n_tasks) load(task);
+  if (task < n_tasks) {
+    load(task);
+    py_job = load_py_rows<N>(a, task, tpw, tpi, pyl);   // with the first tile, one wait for both
+  }
   // the first tile is waited for here, so that the loop head has no loads of its own pending:
   // otherwise the wait the compiler places there for them also drains the previous tile's stores
   // on every later iteration
   vmem_drain();
+  __syncthreads();
   for (; task < n_tasks; task += gridDim.x) {
     float2 v[E];
 #pragma unroll
@@ -563,8 +583,11 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
   };
   int py_job = -1;
   int task = blockIdx.x;
-  if (task < n_tasks) load(task);
-  vmem_drain();   // (as in k_colb)
+  if (task < n_tasks) {
+    load(task);
+    py_job = load_py_rows<N>(a, task, tpw, tpi, pyl);
+  }
+  vmem_drain();   // (as in k_colb; the rows are read after the next barrier)
   for (; task < n_tasks; task += gridDim.x) {
     int wi, col0;
     col_task(a, task, tpw, tpi, wi, col0);
