@@ -428,10 +428,18 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
   float2* twl = lds_mem + (a.pingpong ? 2 : 1) * C * CS;
   float2* pyl = twl + L * NTW;                       // [N] propagator factors of the current job
   // the lane's twiddles stay in registers for the whole kernel (each transform would otherwise
-  // read them from LDS, which the exchanges already keep busy)
-  float2 tw[NTW] = {};
-  PlanOps<P>::twiddles(tw, lx);
-  (void)twl;
+  // read them from LDS, which the exchanges already keep busy); the first L threads evaluate them
+  // once into LDS, every thread copies its lane's
+  if ((int)threadIdx.x < L) {
+    float2 t[NTW] = {};
+    PlanOps<P>::twiddles(t, threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < NTW; ++k) twl[threadIdx.x * NTW + k] = t[k];
+  }
+  __syncthreads();
+  float2 tw[NTW];
+#pragma unroll
+  for (int k = 0; k < NTW; ++k) tw[k] = twl[lx * NTW + k];
   const float2* tab = fft_table_init<P>();   // (lengths that are not powers of two)
   int buf = 0;
   const int s = a.s;
