@@ -146,6 +146,12 @@ template <int AUX> __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t
   __builtin_amdgcn_raw_buffer_store_b64(x, r, opaque(off), 0, AUX);
 }
 
+// a if R, else b (both lvalues; only the chosen branch is instantiated)
+template <bool R, class A, class B> __device__ __forceinline__ decltype(auto) pick_if(A& a, B& b) {
+  if constexpr (R) return (a);
+  else return (b);
+}
+
 // wait for every outstanding memory access of this wavefront
 __device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0); }
 
@@ -218,7 +224,15 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
     }
     __syncthreads();
   }
-  const TwStrided tw{twl + l, L};
+  // E <= 8 plans of the forward pass copy their lane's twiddles to registers (room is left)
+  constexpr bool TWREG = P::POW2 && P::E <= 8 && !ADJ;
+  const TwStrided tws{twl + l, L};
+  float2 twr[TWREG ? P::NTW : 1];
+  if constexpr (TWREG) {
+#pragma unroll
+    for (int k = 0; k < P::NTW; ++k) twr[k] = tws[k];
+  }
+  const auto& tw = pick_if<TWREG>(twr, tws);
   const float2* tab = fft_table_init<P>();
 
   // rows per image rounded up to whole wavefronts of lines (the LINES lines of a wavefront then
