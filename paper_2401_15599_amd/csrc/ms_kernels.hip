@@ -550,9 +550,10 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
       }
     }
     CJob& J = job_at(a.jobs, wv.x);
-    GLOBAL_AS float2* out = pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s);
+    // raw buffer stores: 32-bit element offsets instead of 64-bit addresses per element
+    const __amdgpu_buffer_rsrc_t out = image_rsrc(pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s), nx * N);
 #pragma unroll
-    for (int j = 0; j < E; ++j) out[(ls + L * j) * nx + col0 + cs] = v[j];
+    for (int j = 0; j < E; ++j) bstore<0>(out, (unsigned)((ls + L * j) * nx + col0 + cs) * 8u, v[j]);
   }
 }
 
