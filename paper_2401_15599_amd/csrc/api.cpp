@@ -200,8 +200,8 @@ struct Cached {
 struct Sched {
   int row_plan = 0, col_plan = 0, C = 0;
   int col_kind = 1;    // 0 staged tile, 1 block kernel
-  int pp = 1;          // block kernel: ping-pong LDS exchange regions; 2: and the wave-local
-                       // second exchange (plans with one, tiles of whole wavefronts of columns)
+  int pp = 1;          // block kernel: ping-pong LDS exchange regions; 2: and the split-layout
+                       // transforms (plans with them, tiles of whole wavefronts of columns)
 };
 
 }  // namespace
@@ -1926,7 +1926,7 @@ static std::string sched_line(int n, const Sched& s) {
   std::ostringstream o;
   o << "row=" << plan_name(n, s.row_plan) << " col=" << plan_name(n, s.col_plan) << " C=" << s.C
     << (s.col_kind == 1 ? " block" : s.col_kind == 2 ? " wave-per-column" : " staged")
-    << (s.col_kind == 1 && s.pp ? " pingpong" : "") << (s.col_kind == 1 && s.pp == 2 ? " wave-local-x2" : "");
+    << (s.col_kind == 1 && s.pp ? " pingpong" : "") << (s.col_kind == 1 && s.pp == 2 ? " split-layout" : "");
   return o.str();
 }
 

@@ -72,7 +72,7 @@ struct ColArgs {
   float scale;             // 1/(nx ny), 1/sqrt(nx ny), ...
   int nx;                  // columns per image (all jobs of a launch share nx, ny)
   int pingpong;            // block kernel: two LDS exchange regions (one barrier per exchange);
-                           // 2: also the wave-local second exchange where the plan has one
+                           // 2: also the split-layout transforms where the plan has them
   // Column tiles visited per wave: the first tiles_lo and the last tiles_hi of nx / C (both 0: all).
   // Tiles left out hold only columns outside every job's band; they are neither read nor written.
   // Inside visited tiles, a column outside its job's band is taken as zero (its output is zero
@@ -131,7 +131,7 @@ int col_lds_bytes(int n, int plan, int C);
 bool grid_size_ok(int n);
 int plan_static_lds(int n, int plan);
 bool plan_kind_ok(int n, int plan, int kind);
-int col_block_lx_cols(int n, int plan);   // 0: no wave-local second exchange
+int col_block_lx_cols(int n, int plan);   // 0: no split-layout transforms
 
 // potentials
 hipError_t launch_bin_atoms(const float* xyz, const int* species, int n_snap, int n_atoms,

@@ -1140,7 +1140,7 @@ int plan_static_lds(int n, int plan) {
   return b;
 }
 
-// whether a plan's block y pass has the wave-local second exchange, and its columns per wavefront
+// whether a plan's block y pass has the split-layout transforms, and their columns per wavefront
 int col_block_lx_cols(int n, int plan) {
   int cw = 0;
   with_plan(n, plan, [&](auto p) {
@@ -1294,7 +1294,7 @@ hipError_t launch_col(int n, int plan, int kind, bool dofwd, bool doinv, const C
         else
           hipLaunchKernelGGL((k_colb<P, false, true, PR, LX>), dim3(grid), dim3(threads), lds, st, a);
       };
-      // pingpong == 2: the wave-local second exchange where the tile is whole wavefronts of its
+      // pingpong == 2: the split-layout transforms where the tile is whole wavefronts of their
       // columns (the same results either way)
       auto go = [&](auto pr) {
         if constexpr (colb_lx_ok<P>()) {
