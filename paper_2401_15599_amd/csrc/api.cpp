@@ -526,7 +526,25 @@ struct MsBuild {
   std::vector<MsJobDev> jobs;
   std::vector<ClassPlan> classes;
   MsJobDev* jobs_dev = nullptr;
+  bool entrance = false;   // probe jobs have shared entrance buffers (MsJobDev::entr)
 };
+
+// Batched forward: every probe job gets an entrance buffer of its P positions in the context's
+// workspace; the probe init writes it once and the first x pass of every snapshot reads it (no
+// copy of the entrance wave per snapshot).
+void attach_entrance(tacaw_ctx* c, MsBuild& b) {
+  size_t total = 0;
+  for (const MsJobDev& d : b.jobs)
+    if (d.nap) total += (size_t)d.P * d.nx * d.ny;
+  if (total == 0) return;
+  float2* e = (float2*)workspace(c, "entrance", total * sizeof(float2));
+  for (MsJobDev& d : b.jobs)
+    if (d.nap) {
+      d.entr = e;
+      e += (size_t)d.P * d.nx * d.ny;
+    }
+  b.entrance = true;
+}
 
 MsBuild build_ms(tacaw_ctx* c, int n_jobs, const tacaw_ms_job* jobs, int ckpt_stride, hipStream_t st,
                  bool adjoint, const tacaw_c64* const* gexit, float* const* gV) {
@@ -701,9 +719,11 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
     const Sched rs = schedule_for(c, cp.nx);
     const Sched cs = fit_cols(c, cp.ny, schedule_for(c, cp.ny), cp.nx);
     // the staged init kernels use the same column count (their LDS tile is the smaller one)
+    // entr: probe entrance waves go to (and the first x pass reads them from) the jobs' shared
+    // entrance buffers instead of a copy per snapshot
     auto do_range = [&](hipStream_t sst, const int2* groups, int ng, const int4* waves, const std::vector<int>& gS,
                         const std::vector<int>& wS, const int4* plane, int nplane,
-                        const int4* probe, int nprobe, const int4* copies, int ncopy) {
+                        const int4* probe, int nprobe, const int4* copies, int ncopy, bool entr) {
       Launcher L{c, sst};
       ColArgs ia{};
       ia.jobs = b.jobs_dev;
@@ -719,10 +739,12 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
       if (nprobe > 0) {
         ia.waves = probe;
         ia.n_waves = nprobe;
+        ia.out_buf = entr ? BUF_ENTR : BUF_W;
         long g = std::min<long>((long)nprobe * (cp.nx / cs.C), (long)c->n_cu * 8);
         hip_check(launch_probe_init(cp.ny, cs.col_plan, ia, (int)g, sst), "probe init");
+        ia.out_buf = BUF_W;
       }
-      if (ncopy > 0) {
+      if (ncopy > 0 && !entr) {
         ia.waves = copies;
         ia.n_waves = ncopy;
         const long spans = ((long)cp.nx * cp.ny / 2 + 1023) / 1024;
@@ -736,7 +758,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         ra.groups = groups;
         ra.n_groups = active_prefix(gS, s);
         ra.s = s;
-        ra.in_buf = BUF_W;
+        ra.in_buf = (entr && s == 0) ? BUF_ENTR : BUF_W;
         ra.out_buf = BUF_W;
         ra.store_ckpt = (ckpt_stride > 0 && s % ckpt_stride == 0) ? 1 : 0;
         ra.stash_slot = -1;
@@ -834,7 +856,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
         // the group's waves are contiguous in the class wave list and in the init lists
         const int4* w = waves_dev + wi;
         do_range(st, groups_dev + gi, 1, w, gS, wS, probe ? nullptr : w, probe ? 0 : d.P,
-                 probe ? w : nullptr, probe ? d.P : 0, nullptr, 0);
+                 probe ? w : nullptr, probe ? d.P : 0, nullptr, 0, false);
         wi += d.P;
       }
     } else {
@@ -843,14 +865,15 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
       const int ng = (int)cp.groups.size();
       if (block <= 0.0 || ng < 2) {
         do_range(st, groups_dev, ng, waves_dev, cp.group_S, cp.wave_S, plane_dev,
-                 (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size(), copy_dev, ncopy);
+                 (int)cp.plane_waves.size(), probe_dev, (int)cp.probe_waves.size(), copy_dev, ncopy,
+                 b.entrance);
       } else {
         // entrance waves of the whole class first, then blocks of consecutive snapshots whose
         // waves fit the memory-side cache run all their slices before the next block starts;
         // successive blocks alternate between two streams (forked from and joined back into the
         // caller's), so that one block's launches fill the other's ramp-up and tail
         do_range(st, groups_dev, 0, waves_dev, {}, {}, plane_dev, (int)cp.plane_waves.size(), probe_dev,
-                 (int)cp.probe_waves.size(), copy_dev, ncopy);
+                 (int)cp.probe_waves.size(), copy_dev, ncopy, b.entrance);
         const int chains = fork ? 1 : c->block_streams;
         if (chains > 1) {
           hip_check(hipEventRecord(c->fork_ev, st), "hipEventRecord");
@@ -869,7 +892,7 @@ void run_forward(tacaw_ctx* c, const MsBuild& b, int ckpt_stride, int mode, hipS
           const std::vector<int> gS(cp.group_S.begin() + g0, cp.group_S.begin() + g1);
           const std::vector<int> wS(cp.wave_S.begin() + w0, cp.wave_S.begin() + w1);
           do_range(chains > 1 ? c->side[k % chains] : st, groups_dev + g0, g1 - g0, waves_dev + w0, gS,
-                   wS, nullptr, 0, nullptr, 0, nullptr, 0);
+                   wS, nullptr, 0, nullptr, 0, nullptr, 0, b.entrance);
           g0 = g1;
           ++k;
         }
@@ -1235,6 +1258,7 @@ int tacaw_multislice(tacaw_ctx* ctx, int32_t n_jobs, const tacaw_ms_job* jobs, i
       fail(TACAW_E_ARG, "unknown mode");
     hipStream_t st = (hipStream_t)stream;
     MsBuild b = build_ms(ctx, n_jobs, jobs, ckpt_stride, st, false, nullptr, nullptr);
+    if (mode != TACAW_MODE_PLAIN) attach_entrance(ctx, b);
     b.jobs_dev = upload_vec(ctx, b.jobs, st, "jobs");
     if (mode == TACAW_MODE_PLAIN || ctx->timing) {
       run_forward(ctx, b, ckpt_stride, mode, st);   // timing: eager launches bracketed by events

@@ -27,6 +27,8 @@ struct MsJobDev {
   float2* stash;           // [T][P][K][ny][nx] pre-transmission real-space waves of one segment
   const float2* gexit;     // [T][P][ny][nx]
   float* gV;               // [T][S][ny][nx]
+  float2* entr;            // [P][ny][nx] probe entrance waves shared by all snapshots (batched
+                           // forward), or null
   int T, P, S, nx, ny;
   int kxb;                 // band-limited columns: kx index m is kept by some ky iff
                            // m <= kxb or m >= nx - kxb (nx/2 without a band limit)
@@ -36,7 +38,8 @@ struct MsJobDev {
   double lx, ly, lambda, defocus, cs;
 };
 
-enum Buf : int { BUF_W = 0, BUF_REC = 1, BUF_ADJ = 2, BUF_GEXIT = 3, BUF_CKPT = 4 };
+// BUF_ENTR: a probe job's entrance wave of position (wave mod P) when the job has them, else BUF_W
+enum Buf : int { BUF_W = 0, BUF_REC = 1, BUF_ADJ = 2, BUF_GEXIT = 3, BUF_CKPT = 4, BUF_ENTR = 5 };
 
 __host__ __device__ inline size_t img_off(int wave, int nx, int ny) {
   return (size_t)wave * (size_t)nx * (size_t)ny;

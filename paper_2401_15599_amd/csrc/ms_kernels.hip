@@ -92,6 +92,7 @@ __device__ __forceinline__ GLOBAL_AS float2* pick_buf(CJob& J, int code, int wav
     case BUF_REC: return gp(J.rec) + o;
     case BUF_ADJ: return gp(J.adj) + o;
     case BUF_GEXIT: return gp(const_cast<float2*>(J.gexit)) + o;
+    case BUF_ENTR: return J.entr ? gp(J.entr) + img_off(wave % J.P, J.nx, J.ny) : gp(J.W) + o;
     default: return gp(J.ckpt) + img_off(wave * J.n_ck + s / J.ck_stride, J.nx, J.ny);
   }
 }
