@@ -37,8 +37,24 @@ __global__ __launch_bounds__(kThreads) void k_periodogram(SpecArgs a) {
   float2 tw[P::NTW];
   PlanOps<P>::twiddles(tw, l);
   const long n_tasks = a.nq / QT;
+  // blocks of at most 16 elements per thread are fetched into registers one (position, segment)
+  // block ahead, so that their loads overlap the previous block's transforms
+  constexpr int PER = N * QT / kThreads;
+  constexpr bool PF = (N * QT) % kThreads == 0 && kThreads % QT == 0 && PER <= 16;
+  float2 nxt[PF ? PER : 1];
   for (long task = blockIdx.x; task < n_tasks; task += gridDim.x) {
     const size_t q0 = (size_t)task * QT;
+    // thread: q index threadIdx.x % QT, times threadIdx.x / QT + (kThreads / QT) i (kThreads is a
+    // multiple of QT), so one per-thread base and uniform offsets per (position, segment, i)
+    const size_t tstride = (size_t)a.Ps * a.nq;   // elements from one snapshot to the next
+    const float2* mine = a.exit + (size_t)((int)threadIdx.x / QT) * tstride + q0 + (int)threadIdx.x % QT;
+    auto fetch = [&](int p, int g) {
+      const size_t base = (size_t)(g * a.hop) * tstride + (size_t)(a.p0 + p) * a.nq;
+#pragma unroll
+      for (int i = 0; i < (PF ? PER : 1); ++i)
+        nxt[i] = mine[base + (size_t)(i * (kThreads / QT)) * tstride];
+    };
+    if constexpr (PF) fetch(0, 0);
     float acc[QPASS][E];
 #pragma unroll
     for (int k = 0; k < QPASS; ++k)
@@ -47,10 +63,20 @@ __global__ __launch_bounds__(kThreads) void k_periodogram(SpecArgs a) {
     for (int p = 0; p < a.Pn; ++p) {
       for (int g = 0; g < a.G; ++g) {
         __syncthreads();
-        for (int idx = threadIdx.x; idx < N * QT; idx += kThreads) {
-          const int qi = idx % QT, t = idx / QT;
-          tile[qi * CS + lds_pad(t)] =
-              a.exit[((size_t)(g * a.hop + t) * a.Ps + a.p0 + p) * a.nq + q0 + qi];
+        if constexpr (PF) {
+#pragma unroll
+          for (int i = 0; i < PER; ++i) {
+            const int idx = (int)threadIdx.x + i * kThreads, qi = idx % QT, t = idx / QT;
+            tile[qi * CS + lds_pad(t)] = nxt[i];
+          }
+          const int gn = g + 1 < a.G ? g + 1 : 0, pn = g + 1 < a.G ? p : p + 1;
+          if (pn < a.Pn) fetch(pn, gn);
+        } else {
+          for (int idx = threadIdx.x; idx < N * QT; idx += kThreads) {
+            const int qi = idx % QT, t = idx / QT;
+            tile[qi * CS + lds_pad(t)] =
+                a.exit[((size_t)(g * a.hop + t) * a.Ps + a.p0 + p) * a.nq + q0 + qi];
+          }
         }
         __syncthreads();
 #pragma unroll
