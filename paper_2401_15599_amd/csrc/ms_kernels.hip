@@ -526,11 +526,13 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
     }
     if constexpr (PR) prune_mid<E, 1>(v, 1);   // M is zero there (also for a raw adjoint input)
     {
-      // band-limited propagator (conjugated for the adjoint; pyl is stored conjugated then)
+      // band-limited propagator (conjugated for the adjoint; pyl is stored conjugated then); the
+      // pruned middle registers stay zero
       float2 pxs = cscale(pxm, a.scale);
       if (a.conj_prop) pxs.y = -pxs.y;
 #pragma unroll
       for (int j = 0; j < E; ++j) {
+        if (PR && E >= 4 && (j == E / 2 - 1 || j == E / 2)) continue;
         const int n = lx + L * j;
         const int ns = n < N / 2 ? n : n - N;
         float2 d = cmul(pxs, pyl[n]);
@@ -540,6 +542,7 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
     }
     if constexpr (DOINV) {
       if constexpr (LX) {
+        prune_mid<E, PR ? 1 : 0>(v, 1);   // known zeros for the first (transposed) stage
         wave_lds_sync();
         SF::inv1(v, tw, xreg0, lx);
         wave_lds_sync();
@@ -648,6 +651,7 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
       if (a.conj_prop) pxs.y = -pxs.y;
 #pragma unroll
       for (int j = 0; j < E; ++j) {
+        if (PR && E >= 4 && (j == E / 2 - 1 || j == E / 2)) continue;   // stay zero
         const int n = l + L * j;
         const int ns = n < N / 2 ? n : n - N;
         float2 d = cmul(pxs, pyl[n]);
