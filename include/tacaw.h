@@ -179,7 +179,9 @@ enum {
                               is captured into a hipGraph once per call structure (shapes, slice
                               counts, band, schedule, blocking: not buffer addresses) and
                               replayed; at most 32 graphs are kept per context (least recently
-                              used first out) */
+                              used first out); a probe job's entrance waves are built once into
+                              library workspace (P x ny x nx complex64 per probe job) and read by
+                              the first slice of every snapshot */
   TACAW_MODE_PERSISTENT = 2 /* as BATCHED, with the grid classes of a call as concurrent branches of
                               the captured graph, and square classes of at most 128 points per
                               axis run by one launch of persistent workgroups: each keeps a whole
