@@ -171,8 +171,41 @@ __device__ __forceinline__ void col_task(const ColArgs& a, int task, int tpw, in
   col0 = (jt < a.tiles_lo || a.tiles_hi == 0 ? jt : jt + tpi - a.tiles_lo - a.tiles_hi) * a.C;
 }
 
-// The y pass's propagator rows py of the job of `task` (conjugated for the adjoint) into LDS;
+// (wave index, tile) of the tasks a workgroup visits, advanced by gridDim.x tasks at a time
+// without a division per step
+struct ColCursor {
+  int wi, jt;
+  __device__ __forceinline__ void init(int task, int tpw) {
+    wi = task / tpw;
+    jt = task - wi * tpw;
+  }
+  __device__ __forceinline__ void step(int gdiv, int gmod, int tpw) {
+    wi += gdiv;
+    jt += gmod;
+    if (jt >= tpw) {
+      jt -= tpw;
+      ++wi;
+    }
+  }
+};
+// first column of tile jt of a wave
+__device__ __forceinline__ int col_first(const ColArgs& a, int jt, int tpi) {
+  return (jt < a.tiles_lo || a.tiles_hi == 0 ? jt : jt + tpi - a.tiles_lo - a.tiles_hi) * a.C;
+}
+
+// The y pass's propagator rows py of the job of wave wi (conjugated for the adjoint) into LDS;
 // returns that job.  The caller separates the writes from their readers with a barrier.
+template <int N>
+__device__ __forceinline__ int load_py_rows_w(const ColArgs& a, int wi, float2* pyl) {
+  const int job = const_at(a.waves, wi).x;
+  const GLOBAL_AS float2* pys = gp(job_at(a.jobs, job).py) + a.s * N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    float2 q = pys[i];
+    if (a.conj_prop) q.y = -q.y;
+    pyl[i] = q;
+  }
+  return job;
+}
 template <int N>
 __device__ __forceinline__ int load_py_rows(const ColArgs& a, int task, int tpw, int tpi, float2* pyl) {
   int wi, col0;
@@ -464,9 +497,7 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
   float2 nxt_px = make_float2(0.f, 0.f);
   int nxt_nm = -1;
   // uniform image base + per-lane 32-bit element offsets; a column outside the band reads zeros
-  auto load = [&](int tk) {
-    int wi, col0;
-    col_task(a, tk, tpw, tpi, wi, col0);
+  auto load = [&](int wi, int col0) {
     const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
     const __amdgpu_buffer_rsrc_t in = image_rsrc(pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s), nx * N);
@@ -479,9 +510,14 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
   };
   int py_job = -1;
   int task = blockIdx.x;
+  const int gdiv = (int)gridDim.x / tpw, gmod = (int)gridDim.x - gdiv * tpw;
+  ColCursor cur, nxc;
+  cur.init(task, tpw);
+  nxc = cur;
+  nxc.step(gdiv, gmod, tpw);
   if (task < n_tasks) {
-    load(task);
-    py_job = load_py_rows<N>(a, task, tpw, tpi, pyl);   // with the first tile, one wait for both
+    load(cur.wi, col_first(a, cur.jt, tpi));
+    py_job = load_py_rows_w<N>(a, cur.wi, pyl);   // with the first tile, one wait for both
   }
   // the first tile is waited for here, so that the loop head has no loads of its own pending:
   // otherwise the wait the compiler places there for them also drains the previous tile's stores
@@ -494,8 +530,7 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
     for (int j = 0; j < E; ++j) v[j] = nxt[j];
     const float2 pxm = nxt_px;
     const int nm = nxt_nm;
-    int wi, col0;
-    col_task(a, task, tpw, tpi, wi, col0);
+    const int wi = cur.wi, col0 = col_first(a, cur.jt, tpi);
     const int4 wv = const_at(a.waves, wi);
     // one-way split tiles: the previous tile's readers of the regions are done (with both ways,
     // the other transform's barrier already separates them)
@@ -511,7 +546,9 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
       __syncthreads();
       py_job = wv.x;
     }
-    if (task + (int)gridDim.x < n_tasks) load(task + gridDim.x);
+    if (task + (int)gridDim.x < n_tasks) load(nxc.wi, col_first(a, nxc.jt, tpi));
+    cur = nxc;
+    nxc.step(gdiv, gmod, tpw);
     if constexpr (DOFWD) {
       if constexpr (LX) {
         SF::fwd1(v, reg0, l);
