@@ -97,6 +97,13 @@ __device__ __forceinline__ GLOBAL_AS float2* pick_buf(CJob& J, int code, int wav
   }
 }
 
+// elements from one probe position's image to the next in a buffer kind (for per-position bases
+// derived from the first one)
+__device__ __forceinline__ size_t buf_pos_stride(CJob& J, int code) {
+  const size_t img = (size_t)J.nx * J.ny;
+  return code == BUF_CKPT ? img * J.n_ck : img;
+}
+
 // The x pass streams its rows through HBM once (read once, written once, far larger than the
 // caches): its wave loads and stores carry the non-temporal hint (measured: 3.5 % faster there,
 // 7 % slower in the y pass, whose column tiles keep plain accesses).
@@ -312,11 +319,15 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
 #pragma unroll
     for (int j = 0; j < E; ++j) inb |= (in_band(l + L * j, kxb, N) ? Mask(1) : Mask(0)) << j;
     const Mask rmask = a.band_in ? inb : ~Mask(0), wmask = a.band_out ? inb : ~Mask(0);
+    // the row's wave buffers of position 0; the other positions follow at fixed strides
+    const GLOBAL_AS float2* in_p0 = pick_buf(J, a.in_buf, t * J.P, s);
+    GLOBAL_AS float2* out_p0 = pick_buf(J, a.out_buf, t * J.P, s);
+    const size_t in_ps = buf_pos_stride(J, a.in_buf), out_ps = buf_pos_stride(J, a.out_buf);
     for (int p = 0; p < P_; ++p) {
       const int w = t * J.P + p;
       float2 v[E];
       {
-        const __amdgpu_buffer_rsrc_t in = image_rsrc(pick_buf(J, a.in_buf, w, s), N * ny);
+        const __amdgpu_buffer_rsrc_t in = image_rsrc(in_p0 + p * in_ps, N * ny);
 #pragma unroll
         for (int j = 0; j < E; ++j)
           v[j] = (PR && (j == E / 2 - 1 || j == E / 2))
@@ -358,7 +369,7 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
       }
       if (a.write_out) {
         FFT<P>::template run<false, PR ? 2 : 0>(v, tw, lds, l, tab);
-        const __amdgpu_buffer_rsrc_t out = image_rsrc(pick_buf(J, a.out_buf, w, s), N * ny);
+        const __amdgpu_buffer_rsrc_t out = image_rsrc(out_p0 + p * out_ps, N * ny);
 #pragma unroll
         for (int j = 0; j < E; ++j)
           if (!(PR && (j == E / 2 - 1 || j == E / 2)))
