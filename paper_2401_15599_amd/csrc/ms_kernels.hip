@@ -543,6 +543,10 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
     const int nm = nxt_nm;
     const int wi = cur.wi, col0 = col_first(a, cur.jt, tpi);
     const int4 wv = const_at(a.waves, wi);
+    // the output image is resolved here, while the tile's loads are in flight (raw buffer stores:
+    // 32-bit element offsets instead of 64-bit addresses per element)
+    CJob& J = job_at(a.jobs, wv.x);
+    const __amdgpu_buffer_rsrc_t out = image_rsrc(pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s), nx * N);
     // one-way split tiles: the previous tile's readers of the regions are done (with both ways,
     // the other transform's barrier already separates them)
     if constexpr (LX && !(DOFWD && DOINV)) __syncthreads();
@@ -601,9 +605,6 @@ __global__ __launch_bounds__(colb_max_threads<P>(), (P::POW2 ? 1 : 2)) void k_co
         FFT<P>::template run_block<true, PR ? 1 : 0>(v, tw, reg0, reg1, l, buf, tab);
       }
     }
-    CJob& J = job_at(a.jobs, wv.x);
-    // raw buffer stores: 32-bit element offsets instead of 64-bit addresses per element
-    const __amdgpu_buffer_rsrc_t out = image_rsrc(pick_buf(J, a.out_buf, wv.y * J.P + wv.z, s), nx * N);
 #pragma unroll
     for (int j = 0; j < E; ++j) bstore<0>(out, (unsigned)((ls + L * j) * nx + col0 + cs) * 8u, v[j]);
   }
@@ -642,9 +643,7 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
   // staging: C * N elements per tile over C * 64 / LINES threads = E per thread; C is a power of 2
   const int csh = __builtin_ctz(C), cmask = C - 1;
   float2 nxt[E];
-  auto load = [&](int tk) {
-    int wi, col0;
-    col_task(a, tk, tpw, tpi, wi, col0);
+  auto load = [&](int wi, int col0) {
     const int4 wv = const_at(a.waves, wi);
     CJob& J = job_at(a.jobs, wv.x);
     const __amdgpu_buffer_rsrc_t in = image_rsrc(pick_buf(J, a.in_buf, wv.y * J.P + wv.z, s), nx * N);
@@ -658,14 +657,18 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
   };
   int py_job = -1;
   int task = blockIdx.x;
+  const int gdiv = (int)gridDim.x / tpw, gmod = (int)gridDim.x - gdiv * tpw;
+  ColCursor cur, nxc;   // (as in k_colb)
+  cur.init(task, tpw);
+  nxc = cur;
+  nxc.step(gdiv, gmod, tpw);
   if (task < n_tasks) {
-    load(task);
-    py_job = load_py_rows<N>(a, task, tpw, tpi, pyl);
+    load(cur.wi, col_first(a, cur.jt, tpi));
+    py_job = load_py_rows_w<N>(a, cur.wi, pyl);
   }
   vmem_drain();   // (as in k_colb; the rows are read after the next barrier)
   for (; task < n_tasks; task += gridDim.x) {
-    int wi, col0;
-    col_task(a, task, tpw, tpi, wi, col0);
+    const int wi = cur.wi, col0 = col_first(a, cur.jt, tpi);
     const int4 wv = const_at(a.waves, wi);
     __syncthreads();                                // previous tile fully stored from LDS
 #pragma unroll
@@ -682,7 +685,9 @@ __global__ __launch_bounds__(colw_max_threads<P>()) void k_colw(ColArgs a) {
       }
       py_job = wv.x;
     }
-    if (task + (int)gridDim.x < n_tasks) load(task + gridDim.x);
+    if (task + (int)gridDim.x < n_tasks) load(nxc.wi, col_first(a, nxc.jt, tpi));
+    cur = nxc;
+    nxc.step(gdiv, gmod, tpw);
     __syncthreads();
     CJob& J = job_at(a.jobs, wv.x);
     if (c < C) {
