@@ -319,15 +319,20 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
 #pragma unroll
     for (int j = 0; j < E; ++j) inb |= (in_band(l + L * j, kxb, N) ? Mask(1) : Mask(0)) << j;
     const Mask rmask = a.band_in ? inb : ~Mask(0), wmask = a.band_out ? inb : ~Mask(0);
-    // the row's wave buffers of position 0; the other positions follow at fixed strides
-    const GLOBAL_AS float2* in_p0 = pick_buf(J, a.in_buf, t * J.P, s);
-    GLOBAL_AS float2* out_p0 = pick_buf(J, a.out_buf, t * J.P, s);
-    const size_t in_ps = buf_pos_stride(J, a.in_buf), out_ps = buf_pos_stride(J, a.out_buf);
+    // forward, several positions: the row's wave buffers of position 0, the other positions at
+    // fixed strides (one position per snapshot and the adjoint look each up directly, which keeps
+    // registers free for their longer live state)
+    constexpr bool STRIDED = !ONE && !ADJ;
+    const GLOBAL_AS float2* in_p0 = STRIDED ? pick_buf(J, a.in_buf, t * J.P, s) : nullptr;
+    GLOBAL_AS float2* out_p0 = STRIDED ? pick_buf(J, a.out_buf, t * J.P, s) : nullptr;
+    const size_t in_ps = STRIDED ? buf_pos_stride(J, a.in_buf) : 0;
+    const size_t out_ps = STRIDED ? buf_pos_stride(J, a.out_buf) : 0;
     for (int p = 0; p < P_; ++p) {
       const int w = t * J.P + p;
       float2 v[E];
       {
-        const __amdgpu_buffer_rsrc_t in = image_rsrc(in_p0 + p * in_ps, N * ny);
+        const __amdgpu_buffer_rsrc_t in =
+            image_rsrc(STRIDED ? in_p0 + p * in_ps : pick_buf(J, a.in_buf, w, s), N * ny);
 #pragma unroll
         for (int j = 0; j < E; ++j)
           v[j] = (PR && (j == E / 2 - 1 || j == E / 2))
@@ -369,7 +374,8 @@ __global__ __launch_bounds__(kThreads, (row_min_waves<P, ADJ>())) void k_row(Row
       }
       if (a.write_out) {
         FFT<P>::template run<false, PR ? 2 : 0>(v, tw, lds, l, tab);
-        const __amdgpu_buffer_rsrc_t out = image_rsrc(out_p0 + p * out_ps, N * ny);
+        const __amdgpu_buffer_rsrc_t out =
+            image_rsrc(STRIDED ? out_p0 + p * out_ps : pick_buf(J, a.out_buf, w, s), N * ny);
 #pragma unroll
         for (int j = 0; j < E; ++j)
           if (!(PR && (j == E / 2 - 1 || j == E / 2)))
