@@ -447,8 +447,8 @@ Sched schedule_for(tacaw_ctx* c, int n) {
   // built-in choices: tacaw_autotune on an MI355X over 1 GiB batches of waves per grid size
   // {n, row plan, column plan, C, kind, pp}
   static const int table[][6] = {{16, 1, 1, 16, 1, 1},  {32, 0, 0, 16, 2, 0},  {64, 0, 0, 64, 1, 0},
-                                 {128, 0, 0, 32, 1, 0}, {256, 0, 1, 32, 2, 0}, {512, 0, 0, 16, 1, 2},
-                                 {1024, 0, 0, 8, 2, 0}, {560, 2, 3, 16, 1, 0},  {1000, 1, 1, 8, 1, 1}};
+                                 {128, 0, 0, 32, 1, 0}, {256, 0, 1, 32, 1, 1}, {512, 0, 0, 16, 1, 2},
+                                 {1024, 0, 0, 8, 1, 1}, {560, 2, 3, 16, 1, 0},  {1000, 1, 1, 8, 1, 1}};
   Sched s;
   s.row_plan = 0;
   s.col_plan = 0;

@@ -458,9 +458,9 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col(ColArgs a) {
 // rows l + L j of column c (striped for the column transform), loaded and stored with C-wide row
 // segments.  The next tile is prefetched into registers while the current one is transformed.
 // Twiddles stay in registers; the per-row propagator factors py of the current job sit in LDS.
-// (lengths that are not powers of two: at most 512 threads and 2 wavefronts per SIMD, which leaves
-// their longer lines and table twiddles enough registers)
-template <class P> constexpr int colb_max_threads() { return P::POW2 ? 1024 : 512; }
+// (lengths that are not powers of two and E = 16 plans: at most 512 threads, which leaves their
+// longer lines enough registers; the odd lengths also ask for 2 wavefronts per SIMD)
+template <class P> constexpr int colb_max_threads() { return P::POW2 && P::E <= 8 ? 1024 : 512; }
 
 // LX: the split-layout transforms (SplitFFT; 512 = 8 x 8 x 8) with one workgroup barrier per
 // transform instead of two.  Loads, the first forward stage, the last inverse stage and the stores
