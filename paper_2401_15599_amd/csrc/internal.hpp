@@ -102,6 +102,9 @@ struct PlainArgs {
   // t0 + m / S) are written as exact zeros instead of their partner's rounding residue
   const int* csr = nullptr;
   int csr_t0 = 0, csr_S = 1, csr_nsp = 1;
+  // forward transform of real maps: rows of the result written (0: all); the column band kxb then
+  // selects the column tiles that are transformed and written
+  int rows_out = 0;
 };
 
 // -------- launchers (defined in the .hip files) --------
@@ -160,7 +163,11 @@ struct SfArgs {
 hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st);
 hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, int kxb, int kyb,
                              int pair, const int* csr, int t0, int S, int nsp, hipStream_t st);
-hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, hipStream_t st);
+// forward 2-D DFT of real maps where only the band |kx index| <= kxb (kxb >= nx / 2: all columns)
+// and the rows n < rows_out are wanted: columns of width-C tiles without a kept column are left
+// unwritten, the other columns outside the band hold zeros, rows from rows_out on are unwritten
+hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, int kxb,
+                            int rows_out, hipStream_t st);
 struct PgArgs {
   const float* xyz; const int* order; const int* offsets; const float* ff;
   const float2* gk;        // [maps][ny][nx] DFT of dL/dV
@@ -174,6 +181,7 @@ struct PgArgs {
   const float* vtab;       // [n_species][ny_h][nx] pref M(k) f_Z(|k|) w(k) (ny_h = ny/2 or ny)
   float hbound;            // max over vtab of |v| max(1, |ky|)
   float* absmax_out;       // [n_maps] workspace: max |Re G|, |Im G| over the visited rows
+  int kxb;                 // band columns |kx index| <= kxb: the only columns of G that are set
   // [kx tile][ky fill of 32 rows]: 1 when some k of it passes the band limit (64-wide kx tiles,
   // fills of the visited rows), from the exact band table on the host
   const int* fill_live;

@@ -1002,6 +1002,18 @@ __global__ __launch_bounds__(kThreads) void k_wave_copy(ColArgs a) {
 
 // ------------------------------------------------------------------------------------------------
 // plain batched 2-D transforms of contiguous images
+// column tiles of width C that hold a column kept by the band kxb (all of them for kxb < 0):
+// tiles [0, lo) and [hs, nx / C)
+__host__ __device__ inline void plain_live_tiles(int nx, int C, int kxb, int& lo, int& hs) {
+  const int tpi = nx / C;
+  lo = tpi;
+  hs = tpi;
+  if (kxb >= 0) {
+    lo = min(tpi, kxb / C + 1);
+    hs = max(lo, (nx - kxb) / C);
+  }
+}
+
 template <class P, bool INV, bool REAL_IN, bool REAL_OUT>
 __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_row_plain(PlainArgs a) {
   constexpr int N = P::N, L = P::L, E = P::E, LINES = P::LINES;
@@ -1054,23 +1066,23 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_row_plain(PlainArg
 #pragma unroll
         for (int j = 0; j < E; ++j) out2[l + L * j] = zb ? 0.f : v[j].y;
       }
+    } else if (REAL_IN && a.kxb >= 0 && a.C > 0) {
+      // band-limited forward transform: columns of the column pass's dead tiles are not written,
+      // the other columns outside the band are written as zeros (their column transforms are zero)
+      float2* out = (float2*)a.out + off;
+      int lo, hs;
+      plain_live_tiles(N, a.C, a.kxb, lo, hs);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int m = l + L * j;
+        if (m < lo * a.C || m >= hs * a.C)
+          out[m] = (m > a.kxb && m < N - a.kxb) ? make_float2(0.f, 0.f) : v[j];
+      }
     } else {
       float2* out = (float2*)a.out + off;
 #pragma unroll
       for (int j = 0; j < E; ++j) out[l + L * j] = v[j];
     }
-  }
-}
-
-// column tiles of width C that hold a column kept by the band kxb (all of them for kxb < 0):
-// tiles [0, lo) and [hs, nx / C)
-__host__ __device__ inline void plain_live_tiles(int nx, int C, int kxb, int& lo, int& hs) {
-  const int tpi = nx / C;
-  lo = tpi;
-  hs = tpi;
-  if (kxb >= 0) {
-    lo = min(tpi, kxb / C + 1);
-    hs = max(lo, (nx - kxb) / C);
   }
 }
 
@@ -1129,7 +1141,8 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col_plain(PlainArg
       }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < C * N; idx += kThreads) {
+    const int rows = a.rows_out > 0 ? a.rows_out : N;
+    for (int idx = threadIdx.x; idx < C * rows; idx += kThreads) {
       int c = idx % C, r = idx / C;
       out[(size_t)r * nx + col0 + c] = tile[c * CS + P::pad(r)];
     }
@@ -1497,11 +1510,14 @@ hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, in
   return e;
 }
 
-hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img,
-                            hipStream_t st) {
+hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, int kxb,
+                            int rows_out, hipStream_t st) {
   if (n_img <= 0) return hipSuccess;
+  if (rows_out < 0 || rows_out > ny) return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
-  PlainArgs b{g, gk, n_img, nx, ny, 0};
+  const int C = plain_cols(nx, ny);
+  const int band = kxb >= 0 && kxb < nx / 2 ? kxb : -1;
+  PlainArgs b{g, gk, n_img, nx, ny, C, band};
   with_plan(nx, 0, [&](auto p) {
     using P = decltype(p);
     long tasks = (long)n_img * ny;
@@ -1511,11 +1527,14 @@ hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_im
     e = hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  PlainArgs a{gk, gk, n_img, nx, ny, plain_cols(nx, ny)};
+  PlainArgs a{gk, gk, n_img, nx, ny, C, band};
+  a.rows_out = rows_out;
   with_plan(ny, 0, [&](auto p) {
     using P = decltype(p);
     const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);
-    long tasks = (long)n_img * (nx / a.C);
+    int lo, hs;
+    plain_live_tiles(nx, a.C, band, lo, hs);
+    long tasks = (long)n_img * (lo + (nx / a.C - hs));
     int grid = (int)(tasks < 4096 ? tasks : 4096);
     hipLaunchKernelGGL((k_col_plain<P, false>), dim3(grid), dim3(kThreads), lds, st, a);
     e = hipGetLastError();

@@ -748,11 +748,13 @@ constexpr int kPgRow = 40;    // halves per table row (32 + pad: rows 80 bytes a
 
 // max over the visited rows (n < ny_h) of |Re G| and |Im G|, one workgroup per map
 __global__ __launch_bounds__(256) void k_map_absmax(const float2* gk, int nx, int ny, int ny_h,
-                                                    float* out) {
+                                                    int kxb, float* out) {
   __shared__ float red[256];
   const float2* G = gk + (size_t)blockIdx.x * nx * ny;
   float mx = 0.f;
   for (int i = threadIdx.x; i < ny_h * nx; i += 256) {
+    const int m = i % nx;
+    if (m > kxb && m < nx - kxb) continue;     // columns outside the band are not set
     const float2 g = G[i];
     mx = fmaxf(mx, fmaxf(fabsf(g.x), fabsf(g.y)));
   }
@@ -845,7 +847,8 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
           const int ns = n < a.ny / 2 ? n : n - a.ny;
           const float ky = in ? (float)ns * inv_ly : 0.f;
           const float v = in ? vq[q] * hs : 0.f;
-          const float2 h = make_float2(gq[q].x * v, -gq[q].y * v);
+          // G is set only inside the band (where the table is not zero): outside it, take zero
+          const float2 h = v != 0.f ? make_float2(gq[q].x * v, -gq[q].y * v) : make_float2(0.f, 0.f);
           comps[0][q] = h.x;
           comps[1][q] = h.y;
           comps[2][q] = ky * h.x;
@@ -1062,7 +1065,7 @@ hipError_t launch_position_grad_chunks(const PgArgs& a, const int4* chunks, int 
   if (cap <= 0) return hipSuccess;
   const int ny_h = a.hermitian ? a.ny / 2 : a.ny;
   hipLaunchKernelGGL(k_map_absmax, dim3(a.n_maps), dim3(256), 0, st, a.gk, a.nx, a.ny, ny_h,
-                     a.absmax_out);
+                     a.kxb, a.absmax_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_position_grad, dim3(cap), dim3(256), 0, st, a, chunks, count);
