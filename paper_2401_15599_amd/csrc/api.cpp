@@ -1214,8 +1214,9 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
     const int kxb_g = band_columns(bandlimit_table(*spec));
     for (int t0 = 0; t0 < n_snap; t0 += snaps_per) {
       const int nt = std::min(snaps_per, n_snap - t0);
+      hip_check(launch_zero(absmax, (size_t)nt * S * sizeof(float), st), "zero");
       hip_check(launch_fft2_real(spec->nx, spec->ny, grad_V + (size_t)t0 * S * img, gk, nt * S,
-                                 kxb_g, herm ? spec->ny / 2 : spec->ny, st),
+                                 kxb_g, herm ? spec->ny / 2 : spec->ny, absmax, st),
                 "gradient FFT");
       hip_check(launch_chunk_list(offs, t0, nt, S, n_species, chunks, cap, count, st), "chunk list");
       hip_check(launch_atom_phase(xyz, ord, t0, nt, n_atoms, spec->lx, spec->ly, arec, st),
@@ -1242,9 +1243,8 @@ int tacaw_build_potentials_backward(tacaw_ctx* ctx, const tacaw_specimen* spec, 
       a.hermitian = herm ? 1 : 0;
       a.vtab = vtab;
       a.hbound = (float)hbound;
-      a.absmax_out = absmax;
+      a.absmax = absmax;
       a.fill_live = fill_live;
-      a.kxb = kxb_g;
       timed_launch(ctx, st, "pos_grad", 0.0, [&] {
         hip_check(launch_position_grad_chunks(a, chunks, cap, count, st), "position-gradient kernel");
       });

@@ -105,6 +105,9 @@ struct PlainArgs {
   // forward transform of real maps: rows of the result written (0: all); the column band kxb then
   // selects the column tiles that are transformed and written
   int rows_out = 0;
+  // forward transform: per-map maximum of |Re| and |Im| over the written part of the result
+  // (raised with atomic maxima on the float bits; the caller zeroes it first), or null
+  float* absmax = nullptr;
 };
 
 // -------- launchers (defined in the .hip files) --------
@@ -165,9 +168,11 @@ hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, in
                              int pair, const int* csr, int t0, int S, int nsp, hipStream_t st);
 // forward 2-D DFT of real maps where only the band |kx index| <= kxb (kxb >= nx / 2: all columns)
 // and the rows n < rows_out are wanted: columns of width-C tiles without a kept column are left
-// unwritten, the other columns outside the band hold zeros, rows from rows_out on are unwritten
+// unwritten, the other columns outside the band hold zeros, rows from rows_out on are unwritten.
+// absmax (n_img floats, zeroed by the caller, or null) receives each map's maximum of |Re| and
+// |Im| over the band and the written rows.
 hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, int kxb,
-                            int rows_out, hipStream_t st);
+                            int rows_out, float* absmax, hipStream_t st);
 struct PgArgs {
   const float* xyz; const int* order; const int* offsets; const float* ff;
   const float2* gk;        // [maps][ny][nx] DFT of dL/dV
@@ -180,8 +185,7 @@ struct PgArgs {
   int hermitian;           // visit ky >= 0 only (band limit on)
   const float* vtab;       // [n_species][ny_h][nx] pref M(k) f_Z(|k|) w(k) (ny_h = ny/2 or ny)
   float hbound;            // max over vtab of |v| max(1, |ky|)
-  float* absmax_out;       // [n_maps] workspace: max |Re G|, |Im G| over the visited rows
-  int kxb;                 // band columns |kx index| <= kxb: the only columns of G that are set
+  const float* absmax;     // [n_maps] max |Re G|, |Im G| over the band and the visited rows
   // [kx tile][ky fill of 32 rows]: 1 when some k of it passes the band limit (64-wide kx tiles,
   // fills of the visited rows), from the exact band table on the host
   const int* fill_live;

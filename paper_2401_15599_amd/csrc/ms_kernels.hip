@@ -1142,9 +1142,21 @@ __global__ __launch_bounds__(kThreads, min_waves<P>()) void k_col_plain(PlainArg
     }
     __syncthreads();
     const int rows = a.rows_out > 0 ? a.rows_out : N;
+    float mx = 0.f;
     for (int idx = threadIdx.x; idx < C * rows; idx += kThreads) {
       int c = idx % C, r = idx / C;
-      out[(size_t)r * nx + col0 + c] = tile[c * CS + P::pad(r)];
+      const float2 v = tile[c * CS + P::pad(r)];
+      out[(size_t)r * nx + col0 + c] = v;
+      if constexpr (!INV) mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    if constexpr (!INV) {
+      // the map's maximum: a wavefront maximum, then one atomic maximum per wavefront on the bits
+      // (non-negative floats order as their bit patterns)
+      if (a.absmax) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) atomicMax(reinterpret_cast<unsigned*>(a.absmax) + img, __float_as_uint(mx));
+      }
     }
   }
 }
@@ -1511,7 +1523,7 @@ hipError_t launch_ifft2_real(int nx, int ny, float2* vk, float* V, int n_img, in
 }
 
 hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_img, int kxb,
-                            int rows_out, hipStream_t st) {
+                            int rows_out, float* absmax, hipStream_t st) {
   if (n_img <= 0) return hipSuccess;
   if (rows_out < 0 || rows_out > ny) return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
@@ -1529,6 +1541,7 @@ hipError_t launch_fft2_real(int nx, int ny, const float* g, float2* gk, int n_im
   if (e != hipSuccess) return e;
   PlainArgs a{gk, gk, n_img, nx, ny, C, band};
   a.rows_out = rows_out;
+  a.absmax = absmax;
   with_plan(ny, 0, [&](auto p) {
     using P = decltype(p);
     const int lds = a.C * P::LDS_LINE * (int)sizeof(float2);

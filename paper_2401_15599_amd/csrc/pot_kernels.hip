@@ -746,27 +746,6 @@ hipError_t launch_structure_factor(const SfArgs& a, hipStream_t st) {
 constexpr int kPgKy = 32;     // ky per LDS fill
 constexpr int kPgRow = 40;    // halves per table row (32 + pad: rows 80 bytes apart)
 
-// max over the visited rows (n < ny_h) of |Re G| and |Im G|, one workgroup per map
-__global__ __launch_bounds__(256) void k_map_absmax(const float2* gk, int nx, int ny, int ny_h,
-                                                    int kxb, float* out) {
-  __shared__ float red[256];
-  const float2* G = gk + (size_t)blockIdx.x * nx * ny;
-  float mx = 0.f;
-  for (int i = threadIdx.x; i < ny_h * nx; i += 256) {
-    const int m = i % nx;
-    if (m > kxb && m < nx - kxb) continue;     // columns outside the band are not set
-    const float2 g = G[i];
-    mx = fmaxf(mx, fmaxf(fabsf(g.x), fabsf(g.y)));
-  }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
-}
-
 __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chunks,
                                                       const int* n_chunks) {
   __shared__ __attribute__((aligned(16))) _Float16 Et[4][kChunk][kPgRow];      // y phases (split)
@@ -797,7 +776,7 @@ __global__ __launch_bounds__(256) void k_position_grad(PgArgs a, const int4* chu
   // power-of-two scale of H for this map
   float hs = 1.f;
   {
-    const float b = a.absmax_out[map] * a.hbound;
+    const float b = a.absmax[map] * a.hbound;
     if (b > 0.f && b < 3.0e38f) {
       int e;
       (void)frexpf(b, &e);                      // b <= 2^e
@@ -1063,11 +1042,6 @@ hipError_t launch_chunk_list(const int* offsets, int t0, int nt, int S, int nsp,
 hipError_t launch_position_grad_chunks(const PgArgs& a, const int4* chunks, int cap,
                                        const int* count, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
-  const int ny_h = a.hermitian ? a.ny / 2 : a.ny;
-  hipLaunchKernelGGL(k_map_absmax, dim3(a.n_maps), dim3(256), 0, st, a.gk, a.nx, a.ny, ny_h,
-                     a.kxb, a.absmax_out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_position_grad, dim3(cap), dim3(256), 0, st, a, chunks, count);
   return hipGetLastError();
 }
