@@ -66,6 +66,8 @@ def parse():
                    help="run only the 560^2 and 1000^2 lines (for kernel traces of their passes)")
     p.add_argument("--large-only", action="store_true",
                    help="run only the large configuration at full size (1024^2, 2048 snapshots)")
+    p.add_argument("--adjoint-only", action="store_true",
+                   help="run only the adjoint line (256^2 differentiation workload)")
     p.add_argument("--summarize-traffic", nargs=4,
                    metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_RUN_JSON", "OUT_JSON"),
                    help="turn two rocprofv3 counter files (FETCH_SIZE, WRITE_SIZE) of a --calibrate "
@@ -725,6 +727,10 @@ def main():
     if args.large_only:
         import paper_2401_15599_amd as tw
         print(json.dumps({"large": large_run(tw)}))
+        return
+    if args.adjoint_only:
+        import paper_2401_15599_amd as tw
+        print(json.dumps({"adjoint": adjoint_leg(tw)}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
