@@ -554,3 +554,31 @@ def test_gradients_match_oracle(stride, n):
     check(V.grad.cpu().numpy(), ref["gV"], 1e-3)
     check(xyz.grad.cpu().numpy()[..., :2], ref["gxy"], 1e-3)
     assert float(xyz.grad[..., 2].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_position_gradient_ignores_stale_workspace(n):
+    # (at 256 the DFT's 16-column tiles 96..159 hold no kept kx and are skipped; at 128 every
+    # 32-column tile is kept and only the rows ky < 0 are left out)
+    # With a band limit the gradient's DFT leaves the columns of skipped tiles (and, on the half
+    # plane, the rows ky < 0) unwritten.  A previous call on the same context without a band limit
+    # and with a NaN dL/dV fills the whole shared workspace with NaN; the band-limited call after it
+    # must still match the oracle (the unwritten entries are taken as zero, not multiplied by zero).
+    spec, _, pos, species, ff, *_ = _grad_problem(3, n)
+    T, S, na = pos.shape[0], len(spec.dz), pos.shape[1]
+    gV = np.random.default_rng(5).normal(size=(T, S, n, n)).astype(np.float32)
+    ref = np.stack([o_adj.position_gradient(gV[t].astype(np.float64), pos[t], species, ff, spec)
+                    for t in range(T)])
+    c = tw.Context(0)
+    xyz, sp = _gpu(pos), _gpu(species)
+    gxy = torch.empty((T, na, 2), dtype=torch.float32, device=DEV)
+    full = SimpleNamespace(**{**vars(spec), "bandlimit": 0.0})
+    nan_gV = torch.full((T, S, n, n), float("nan"), dtype=torch.float32, device=DEV)
+    tw.tacaw_build_potentials_backward(c, tw.specimen_from(full), xyz, sp, ff, nan_gV, gxy)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(gxy).any())
+    tw.tacaw_build_potentials_backward(c, tw.specimen_from(spec), xyz, sp, ff, _gpu(gV), gxy)
+    torch.cuda.synchronize()
+    out = gxy.cpu().numpy()
+    assert np.isfinite(out).all()
+    check(out, ref, 1e-3)
