@@ -122,7 +122,8 @@ def test_smallest_grid_with_probe():
 
 
 def test_largest_grid():
-    # 1024^2: the y pass takes the wave-per-column kernel, the x pass the 16-element plans
+    # 1024^2: the x pass and the y pass take the 16-element plans (the y pass as the block kernel
+    # on 512 threads)
     spec, pos, species = _specimen(1024, 320.0, [2.0, 2.0], 400, 1, 4)
     V, Vr, ex = _pipeline(spec, pos, species, PLANE)
     assert rel_l2(V, Vr) <= 1e-5

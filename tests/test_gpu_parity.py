@@ -227,7 +227,7 @@ def test_multislice_uneven_batch_in_one_call():
             check(out.cpu().numpy(), ref, 1e-4)
 
 
-@pytest.mark.parametrize("n", [64, 256, 512, 560, 1000])
+@pytest.mark.parametrize("n", [64, 256, 512, 560, 1000, 1024])
 def test_every_fft_schedule_matches_oracle(n, tmp_path):
     """Each compiled x-pass plan, y-pass plan, y-pass kernel kind and tile width gives the same
     exit waves (same transform, different blocking).  A wave-per-column request that no column
